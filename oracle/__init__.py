@@ -1,0 +1,268 @@
+"""FP64 CPU oracle for the valency-bounding correction (VBC), arXiv 2609.07842.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+(``paper_2609_07842_amd``) never imports it, and the two share no code.
+
+The numerical work is in ``vbc_oracle.c`` (plain O(N^2) definitions in FP64,
+built with ``-ffp-contract=off``); this module only builds that file with gcc
+and marshals numpy arrays through ctypes.  Positions are N x 3 row-major here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vbc_oracle.c")
+_LIB = os.path.join(_HERE, "libvbc_oracle.so")
+
+PAIR_FIELDS = ("E_r", "r_r", "E_a", "r_a", "r_l", "r_h", "f", "delta")
+
+
+class Pair(C.Structure):
+    _fields_ = [(k, C.c_double) for k in PAIR_FIELDS]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        i64p = C.POINTER(C.c_int64)
+        i32p = C.POINTER(C.c_int32)
+        u32p = C.POINTER(C.c_uint32)
+        u64p = C.POINTER(C.c_uint64)
+        pp = C.POINTER(Pair)
+        for name in ("vbco_omega", "vbco_omega_d"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double] * 3
+        for name in ("vbco_Vr", "vbco_Vr_d_over_r"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double] * 3
+        for name in ("vbco_Va", "vbco_Va_d"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double] * 4
+        L.vbco_neighbor_pairs.restype = C.c_int64
+        L.vbco_neighbor_pairs.argtypes = [C.c_int64, dp, dp, C.c_double, i64p, C.c_int64]
+        L.vbco_counts.restype = None
+        L.vbco_counts.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, u32p, dp]
+        L.vbco_eval.restype = None
+        L.vbco_eval.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, u32p, dp, dp, dp, dp, dp]
+        L.vbco_eval_subset.restype = None
+        L.vbco_eval_subset.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, u32p, i64p,
+                                       C.c_int64, dp, dp, dp]
+        L.vbco_bonds.restype = C.c_double
+        L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp]
+        L.vbco_philox4x64_10.restype = None
+        L.vbco_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.vbco_noise.restype = None
+        L.vbco_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, dp]
+        L.vbco_run.restype = None
+        L.vbco_run.argtypes = [C.c_int64, dp, dp, i32p, i64p, dp, C.c_int, pp, u32p, i64p,
+                               C.c_int64, C.c_double, C.c_double, C.c_int, C.c_double,
+                               C.c_double, C.c_double, C.c_uint64, C.c_uint64, C.c_int64,
+                               dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def pair_table(params, ntypes: int = 1):
+    """params: dict (single type) or list of ntypes*ntypes dicts (row-major, symmetric)."""
+    if isinstance(params, dict):
+        params = [params]
+    if len(params) != ntypes * ntypes:
+        raise ValueError("need ntypes^2 pair entries")
+    arr = (Pair * len(params))()
+    for k, p in enumerate(params):
+        for f in PAIR_FIELDS:
+            setattr(arr[k], f, float(p[f]))
+    return arr
+
+
+def _sys_args(x, L, params, types, mask):
+    x = _f64(x)
+    N = x.shape[0]
+    L = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy())
+    if isinstance(params, dict):
+        ntypes = 1
+    else:
+        ntypes = int(round(len(params) ** 0.5))
+    tab = pair_table(params, ntypes)
+    if types is not None:
+        types = np.ascontiguousarray(types, dtype=np.int32)
+        tp = types.ctypes.data_as(C.POINTER(C.c_int32))
+    else:
+        tp = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint32)
+        mp = mask.ctypes.data_as(C.POINTER(C.c_uint32))
+    else:
+        mp = None
+    return x, N, L, ntypes, tab, types, tp, mask, mp
+
+
+# ---------------------------------------------------------------------------
+# public wrappers
+# ---------------------------------------------------------------------------
+
+def omega(x, x1, x2):
+    return lib().vbco_omega(float(x), float(x1), float(x2))
+
+
+def omega_d(x, x1, x2):
+    return lib().vbco_omega_d(float(x), float(x1), float(x2))
+
+
+def V_r(r, E_r, r_r):
+    return lib().vbco_Vr(float(r), float(E_r), float(r_r))
+
+
+def V_r_d_over_r(r, E_r, r_r):
+    return lib().vbco_Vr_d_over_r(float(r), float(E_r), float(r_r))
+
+
+def V_a(r, E_a, r_r, r_a):
+    return lib().vbco_Va(float(r), float(E_a), float(r_r), float(r_a))
+
+
+def V_a_d(r, E_a, r_r, r_a):
+    return lib().vbco_Va_d(float(r), float(E_a), float(r_r), float(r_a))
+
+
+def neighbor_pairs(x, L, rc):
+    """All pairs i<j with minimum-image r^2 < rc^2, lexicographic, shape (P, 2)."""
+    x = _f64(x)
+    Lv = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy())
+    N = x.shape[0]
+    cap = max(16, N * 8)
+    while True:
+        out = np.zeros((cap, 2), dtype=np.int64)
+        n = lib().vbco_neighbor_pairs(N, _dp(x), _dp(Lv), float(rc),
+                                      out.ctypes.data_as(C.POINTER(C.c_int64)), cap)
+        if n <= cap:
+            return out[:n].copy()
+        cap = int(n)
+
+
+def counts(x, L, params, types=None, mask=None):
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
+    n = np.zeros(N)
+    lib().vbco_counts(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n))
+    return n
+
+
+def evaluate(x, L, params, types=None, mask=None):
+    """Full evaluation.  Returns dict with n, A, F (N x 3), e, U, W, Wt (6)."""
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
+    n = np.zeros(N)
+    A = np.zeros(N)
+    F = np.zeros((N, 3))
+    e = np.zeros(N)
+    UW = np.zeros(8)
+    lib().vbco_eval(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n), _dp(A), _dp(F), _dp(e), _dp(UW))
+    return {"n": n, "A": A, "F": F, "e": e, "U": UW[0], "W": UW[1], "Wt": UW[2:8].copy()}
+
+
+def evaluate_subset(x, L, params, idx, types=None, mask=None):
+    """n, F (m x 3) and e of the particles idx of a (possibly large) system."""
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    m = idx.shape[0]
+    n = np.zeros(m)
+    F = np.zeros((m, 3))
+    e = np.zeros(m)
+    lib().vbco_eval_subset(N, _dp(x), tp, _dp(Lv), nt, tab, mp,
+                           idx.ctypes.data_as(C.POINTER(C.c_int64)), m, _dp(n), _dp(F), _dp(e))
+    return {"n": n, "F": F, "e": e}
+
+
+def bonds_energy_forces(x, L, bonds, k, r0):
+    x = _f64(x)
+    N = x.shape[0]
+    Lv = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy())
+    b = np.ascontiguousarray(bonds, dtype=np.int64).reshape(-1, 2)
+    F = np.zeros((N, 3))
+    U = lib().vbco_bonds(N, _dp(x), _dp(Lv), b.ctypes.data_as(C.POINTER(C.c_int64)),
+                         b.shape[0], float(k), float(r0), _dp(F))
+    return U, F
+
+
+def philox4x64_10(counter, key):
+    c = (C.c_uint64 * 4)(*[int(v) for v in counter])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib().vbco_philox4x64_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def noise(seed, tag, step):
+    xi = np.zeros(3)
+    lib().vbco_noise(int(seed), int(tag), int(step), _dp(xi))
+    return xi
+
+
+NVE, LANGEVIN = 0, 1
+
+
+def run(x, v, L, params, nsteps, kind=NVE, dt=0.005, kT=1.0, gamma=0.1, seed=0, step0=0,
+        types=None, mask=None, tags=None, bonds=None, k_bond=0.0, r0=1.0, history=False):
+    """Integrate in place on copies; returns dict x, v, F (+ U, K histories)."""
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
+    x = x.copy()
+    v = _f64(v).copy()
+    if tags is not None:
+        tags = np.ascontiguousarray(tags, dtype=np.int64)
+        tg = tags.ctypes.data_as(C.POINTER(C.c_int64))
+    else:
+        tg = None
+    if bonds is not None:
+        bonds = np.ascontiguousarray(bonds, dtype=np.int64).reshape(-1, 2)
+        bp, nb = bonds.ctypes.data_as(C.POINTER(C.c_int64)), bonds.shape[0]
+    else:
+        bp, nb = None, 0
+    F = np.zeros((N, 3))
+    Uh = np.zeros(max(nsteps, 1)) if history else None
+    Kh = np.zeros(max(nsteps, 1)) if history else None
+    lib().vbco_run(N, _dp(x), _dp(v), tp, tg, _dp(Lv), nt, tab, mp, bp, nb, float(k_bond),
+                   float(r0), int(kind), float(dt), float(kT), float(gamma), int(seed),
+                   int(step0), int(nsteps), _dp(F), _dp(Uh), _dp(Kh))
+    out = {"x": x, "v": v, "F": F}
+    if history:
+        out["U"] = Uh[:nsteps]
+        out["K"] = Kh[:nsteps]
+    return out
