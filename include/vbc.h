@@ -1,0 +1,178 @@
+/*
+ * vbc.h -- C ABI of libvbc.so, the MI355X (gfx950) hot path of the valency-bounding
+ * correction (VBC): Dmitriev, Gupta & Goloborodko, "Valency-bounding correction
+ * potential for coarse-grained molecular dynamics simulations", arXiv 2609.07842.
+ *
+ * The library evaluates, for one or more independent periodic particle systems
+ * ("replicas") resident in GPU memory:
+ *   U = sum_{i<j} [ V_r(r_ij) + Psi(n_i, n_j) V_a(r_ij) ]          Section 2, eq. (Vhat)
+ *   n_i = sum_{j != i} omega(r_ij, r_l, r_h)                          eq. (counter)
+ *   Psi = omega(n_i, f-delta, f-delta+1) omega(n_j, f-delta, f-delta+1)   eq. (Psi), (Psidelta)
+ * with the polynomial soft-core V_r, V_a of eq. (softcore), the smooth step omega of
+ * eq. (omega), and the forces -grad U including the chain-rule terms through dPsi/dn.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns a vbc_status; nothing throws across the ABI.  On error
+ *    vbc_last_error(h) returns a message owned by the handle (valid until the next call).
+ *  - "Device" pointers are HIP device memory owned by the caller.  The library allocates
+ *    no device memory at all: all of its state lives in the caller-provided workspace
+ *    (size from vbc_workspace_size), which must stay alive until vbc_destroy.
+ *  - Calls that take a hipStream_t are asynchronous on that stream and launch only
+ *    kernels (no allocation, no host synchronisation, no memset nodes), so they may be
+ *    captured into a HIP graph.  Conditions detected on the GPU (list or staging
+ *    overflow, non-finite coordinates) are latched per replica in the workspace and
+ *    reported by vbc_check, which synchronises the stream.
+ *  - Per-particle caller arrays are structure-of-arrays over the concatenation of all
+ *    replicas in replica order ("caller order"): replica r occupies indices
+ *    [o_r, o_r + N_r) with o_r = N_0 + ... + N_{r-1}; inside a replica, index = tag,
+ *    the particle's position in the arrays given to vbc_set_state.  A 3-vector array
+ *    holds all x components, then all y, then all z (stride Ntot = sum of N_r).
+ *  - Units: unit masses; energies in the units of E_r, E_a; kT in the same units.
+ */
+#ifndef VBC_H
+#define VBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vbc_status;
+enum {
+    VBC_OK = 0,
+    VBC_ERR_ARG = 1,            /* invalid argument or parameter set */
+    VBC_ERR_BOX = 2,            /* box shorter than 2 x (cutoff + skin), or fewer than 3 cells */
+    VBC_ERR_NLIST_OVERFLOW = 3, /* a particle had more list neighbours than k_max */
+    VBC_ERR_NONFINITE = 4,      /* a coordinate became NaN or infinite */
+    VBC_ERR_HIP = 5,            /* a HIP runtime call failed */
+    VBC_ERR_CAPACITY = 6,       /* a cell brick held more particles than the staging capacity,
+                                   or the workspace is too small */
+    VBC_ERR_UNIMPLEMENTED = 7,
+    VBC_ERR_STATE = 8           /* call out of order (e.g. no state set yet) */
+};
+
+/* Bits of the per-replica flag word reported by vbc_check. */
+enum {
+    VBC_FLAG_REBUILD = 1u,         /* internal: list rebuild pending */
+    VBC_FLAG_NLIST_OVERFLOW = 2u,
+    VBC_FLAG_STAGE_OVERFLOW = 4u,
+    VBC_FLAG_NONFINITE = 8u
+};
+
+/* Parameters of one type pair (Section 2, eq. (softcore); eq. (counter); eq. (Psidelta)).
+ * Requires 0 <= E_r, 0 <= E_a, 0 < r_r < r_a, 0 < r_l < r_h.  f and delta are real. */
+typedef struct {
+    double E_r, r_r; /* repulsive core height and range */
+    double E_a, r_a; /* attractive well depth and outer range (well centred at (r_a+r_r)/2) */
+    double r_l, r_h; /* counting radii: a neighbour counts 1 below r_l, 0 above r_h */
+    double f, delta; /* valency cap and switching shift (threshold f - delta) */
+} vbc_pair_params;
+
+enum { VBC_FP64 = 0, VBC_FP32_MIXED = 1 };
+
+/* One replica (independent periodic system).  Host memory; copied by vbc_create. */
+typedef struct {
+    int64_t n;                      /* particles, >= 1 */
+    double L[3];                    /* orthorhombic periodic box edges */
+    int32_t ntypes;                 /* 1..4 particle types */
+    const vbc_pair_params *params;  /* ntypes x ntypes row-major, must be symmetric */
+    const uint32_t *count_mask;     /* ntypes words: bit u of word t set => a particle of type
+                                       t counts neighbours of type u; NULL = all count all */
+    double skin;                    /* neighbour-list buffer added to the largest cutoff */
+    int32_t chain_len;              /* > 1: tags form chains of this many consecutive beads
+                                       joined by harmonic bonds; 0 = no bonds */
+    double k_bond, r0_bond;         /* bond energy k/2 (r - r0)^2 */
+} vbc_replica_desc;
+
+/* Layout and launch knobs (0 = automatic).  None of them changes a result beyond the
+ * rounding of sums. */
+typedef struct {
+    int32_t precision;   /* VBC_FP64 or VBC_FP32_MIXED (FP32 pair arithmetic, FP64
+                            counts, switching, integration and reductions) */
+    int32_t k_max;       /* neighbour-list slots per particle */
+    int32_t brick;       /* cells per edge of the cell brick one workgroup owns (1..6) */
+    int32_t block;       /* threads per workgroup for brick kernels (64..1024, multiple of 64) */
+    int32_t stage_cap;   /* particles staged in LDS per brick (own + halo) */
+} vbc_options;
+
+enum { VBC_NVE = 0, VBC_LANGEVIN = 1 };
+
+/* Integrator.  NVE: velocity Verlet.  LANGEVIN: BAOAB splitting with friction gamma at
+ * temperature kT; noise from Philox4x64-10 keyed by (seed, tag), counter (step, 0, 0, 0),
+ * each of the first three words mapped to sqrt(3) (2u - 1), u = (word >> 11) 2^-53. */
+typedef struct {
+    int32_t kind;
+    double dt, kT, gamma;
+    uint64_t seed;
+} vbc_integrator;
+
+typedef struct vbc_handle_s *vbc_handle;
+
+/* Bytes of device workspace needed for these replicas and options. */
+vbc_status vbc_workspace_size(const vbc_replica_desc *reps, int32_t nrep,
+                              const vbc_options *opt, size_t *bytes);
+
+/* Validate the parameters, lay out the workspace d_ws (device, >= the size above, at
+ * least 256-byte aligned), upload the static tables on stream s and return a handle.
+ * Fails with VBC_ERR_ARG for unphysical or asymmetric parameters and VBC_ERR_BOX for a
+ * box that cannot hold the minimum image at the list radius. */
+vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt,
+                      void *d_ws, size_t ws_bytes, hipStream_t s, vbc_handle *out);
+vbc_status vbc_destroy(vbc_handle h);
+const char *vbc_last_error(vbc_handle h);
+
+/* Copy positions (device, 3 x N SoA, caller order; any real values, wrapped into the box),
+ * velocities (device, same layout, or NULL for zero) and types (device int32 [N], or NULL
+ * for type 0) of replica rep (or of all replicas if rep < 0, then N = Ntot) into the
+ * library, reset that replica's step counter to step0 and mark its list stale. */
+vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const double *d_v,
+                         const int32_t *d_type, uint64_t step0, hipStream_t s);
+
+/* Copy positions (wrapped into [0, L)) and velocities of replica rep (or all if rep < 0)
+ * out in caller order.  Either pointer may be NULL. */
+vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hipStream_t s);
+
+/* Neighbour-list build (Section 5: list at the largest cutoff plus a buffer): wrap
+ * positions into the box, bin into cells of edge >= r_list, sort particles by cell
+ * (ties by tag), and list for every particle all j != i with minimum-image squared
+ * distance < r_list^2, evaluated in FP64 without contraction.  Resets the displacement
+ * reference. */
+vbc_status vbc_build_nlist(vbc_handle h, hipStream_t s);
+
+/* Pass 1 (Section 2, eq. (counter)): smoothed neighbour counts n_i in FP64, written to
+ * d_n (device, [Ntot], caller order) unless NULL.  Rebuilds the list first if stale. */
+vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s);
+
+/* Passes 1 and 2 (Section 2, two-passes paragraph): forces -grad U into d_F (device,
+ * 3 x Ntot SoA, caller order), per-particle energies (half of each pair energy, plus half
+ * of each bond energy) into d_e ([Ntot]) and per replica 8 doubles into d_UW
+ * ({U, W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz} with W = -sum_{i<j} dU/dr_ij r_ij);
+ * each pointer may be NULL. */
+vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipStream_t s);
+
+/* Advance every replica by nsteps steps of the integrator.  The list is rebuilt on the
+ * GPU whenever some particle of a replica has moved more than skin/2 since the last build. */
+vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s);
+
+/* Synchronise s and report the flag word of each replica (host array [nrep], may be NULL);
+ * returns the first error among them (overflow or non-finite) and clears the error bits. */
+vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica);
+
+/* The current neighbour list of replica rep as tag pairs: for every particle i and
+ * every listed j, (tag_i, tag_j) into d_pairs (device int32, 2 x cap interleaved); the
+ * number of pairs into *d_count (device int64).  Pairs beyond cap are counted, not
+ * written.  Test and inspection aid. */
+vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t cap,
+                         int64_t *d_count, hipStream_t s);
+
+/* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
+vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBC_H */

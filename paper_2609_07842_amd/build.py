@@ -1,0 +1,65 @@
+"""Build libvbc.so (HIP kernels for gfx950 + the C ABI of include/vbc.h) in-tree.
+
+    python -m paper_2609_07842_amd.build
+
+hipcc cross-compiles for gfx950 without a GPU.  Packed FP32 instructions are switched
+off for all device code, and contraction into FMA is allowed except where a function
+turns it off with a pragma (the exact FP64 list distance and the integrator).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libvbc.so")
+SOURCES = ["vbc_kernels.hip", "vbc_api.hip"]
+ARCH = os.environ.get("VBC_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def flags() -> list[str]:
+    return [
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+        "-ffp-contract=fast-honor-pragmas",
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+        f"-I{os.path.join(HERE, '..', 'include')}",
+    ]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link libvbc.so next to this file."""
+    objs = []
+    cc = hipcc()
+    for src in SOURCES:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print(LIB)
+    sys.exit(0)

@@ -1,0 +1,290 @@
+"""ctypes binding of libvbc.so (include/vbc.h) with the same entry-point names.
+
+Only argument marshalling lives here: device memory comes from torch tensors, the
+stream is torch's current stream, and every computation runs in the library's HIP
+kernels.  Importing this module fails loudly if libvbc.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvbc.so")
+
+VBC_OK, VBC_ERR_ARG, VBC_ERR_BOX, VBC_ERR_NLIST_OVERFLOW, VBC_ERR_NONFINITE, VBC_ERR_HIP, \
+    VBC_ERR_CAPACITY, VBC_ERR_UNIMPLEMENTED, VBC_ERR_STATE = range(9)
+STATUS_NAMES = {0: "VBC_OK", 1: "VBC_ERR_ARG", 2: "VBC_ERR_BOX", 3: "VBC_ERR_NLIST_OVERFLOW",
+                4: "VBC_ERR_NONFINITE", 5: "VBC_ERR_HIP", 6: "VBC_ERR_CAPACITY",
+                7: "VBC_ERR_UNIMPLEMENTED", 8: "VBC_ERR_STATE"}
+FLAG_REBUILD, FLAG_NLIST_OVERFLOW, FLAG_STAGE_OVERFLOW, FLAG_NONFINITE = 1, 2, 4, 8
+FP64, FP32_MIXED = 0, 1
+NVE, LANGEVIN = 0, 1
+
+# every symbol include/vbc.h declares
+EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", "vbc_set_state",
+           "vbc_get_state", "vbc_build_nlist", "vbc_count", "vbc_force", "vbc_step", "vbc_check",
+           "vbc_get_nlist", "vbc_get_options")
+
+
+class PairParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E_r", "r_r", "E_a", "r_a", "r_l", "r_h", "f", "delta")]
+
+
+class ReplicaDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("L", C.c_double * 3), ("ntypes", C.c_int32),
+                ("params", C.POINTER(PairParams)), ("count_mask", C.POINTER(C.c_uint32)),
+                ("skin", C.c_double), ("chain_len", C.c_int32), ("k_bond", C.c_double),
+                ("r0_bond", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("k_max", C.c_int32), ("brick", C.c_int32),
+                ("block", C.c_int32), ("stage_cap", C.c_int32)]
+
+
+class Integrator(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("kT", C.c_double),
+                ("gamma", C.c_double), ("seed", C.c_uint64)]
+
+
+class VBCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2609_07842_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_void_p
+        sig = {
+            "vbc_workspace_size": [C.POINTER(ReplicaDesc), i32, C.POINTER(Options), C.POINTER(C.c_size_t)],
+            "vbc_create": [C.POINTER(ReplicaDesc), i32, C.POINTER(Options), vp, C.c_size_t, vp,
+                           C.POINTER(vp)],
+            "vbc_destroy": [vp],
+            "vbc_set_state": [vp, i32, dp, dp, dp, u64, vp],
+            "vbc_get_state": [vp, i32, dp, dp, vp],
+            "vbc_build_nlist": [vp, vp],
+            "vbc_count": [vp, dp, vp],
+            "vbc_force": [vp, dp, dp, dp, vp],
+            "vbc_step": [vp, i32, C.POINTER(Integrator), vp],
+            "vbc_check": [vp, vp, C.POINTER(C.c_uint32)],
+            "vbc_get_nlist": [vp, i32, dp, i64, dp, vp],
+            "vbc_get_options": [vp, C.POINTER(Options)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int32
+        L.vbc_last_error.argtypes = [vp]
+        L.vbc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st, h=None):
+    if st != VBC_OK:
+        msg = lib().vbc_last_error(h)
+        raise VBCError(st, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _pair_array(params, ntypes):
+    if isinstance(params, dict):
+        params = [params]
+    if len(params) != ntypes * ntypes:
+        raise ValueError("need ntypes^2 pair entries")
+    arr = (PairParams * len(params))()
+    for k, p in enumerate(params):
+        for f in ("E_r", "r_r", "E_a", "r_a", "r_l", "r_h", "f", "delta"):
+            setattr(arr[k], f, float(p[f]))
+    return arr
+
+
+def replica(n, L, params, mask=None, skin=0.4, chain_len=0, k_bond=0.0, r0_bond=1.0):
+    """Description of one replica (host side).  params: dict or list of ntypes^2 dicts."""
+    ntypes = 1 if isinstance(params, dict) else int(round(len(params) ** 0.5))
+    return dict(n=int(n), L=np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy(),
+                params=params, ntypes=ntypes, mask=None if mask is None else np.asarray(mask, np.uint32),
+                skin=float(skin), chain_len=int(chain_len), k_bond=float(k_bond), r0_bond=float(r0_bond))
+
+
+def _descs(reps):
+    arr = (ReplicaDesc * len(reps))()
+    keep = []
+    for k, r in enumerate(reps):
+        pa = _pair_array(r["params"], r["ntypes"])
+        keep.append(pa)
+        d = arr[k]
+        d.n = r["n"]
+        for a in range(3):
+            d.L[a] = float(r["L"][a])
+        d.ntypes = r["ntypes"]
+        d.params = C.cast(pa, C.POINTER(PairParams))
+        if r["mask"] is not None:
+            m = (C.c_uint32 * r["ntypes"])(*[int(v) for v in r["mask"]])
+            keep.append(m)
+            d.count_mask = C.cast(m, C.POINTER(C.c_uint32))
+        else:
+            d.count_mask = None
+        d.skin = r["skin"]
+        d.chain_len = r["chain_len"]
+        d.k_bond = r["k_bond"]
+        d.r0_bond = r["r0_bond"]
+    return arr, keep
+
+
+def _options(precision="fp64", k_max=0, brick=0, block=0, stage_cap=0):
+    o = Options()
+    o.precision = FP64 if precision in ("fp64", FP64) else FP32_MIXED
+    o.k_max, o.brick, o.block, o.stage_cap = int(k_max), int(brick), int(block), int(stage_cap)
+    return o
+
+
+def workspace_size(reps, precision="fp64", **opts):
+    """Workspace bytes for a list of replica descriptions (host-only; no GPU needed)."""
+    arr, keep = _descs(reps)
+    o = _options(precision, **opts)
+    n = C.c_size_t(0)
+    st = lib().vbc_workspace_size(arr, len(reps), C.byref(o), C.byref(n))
+    _check(st)
+    return int(n.value)
+
+
+def _soa(t, n, torch, device, dtype):
+    """(n, 3) numpy/torch -> contiguous (3, n) device tensor."""
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device=device, dtype=dtype)
+    if t.dim() == 2 and t.shape == (n, 3):
+        t = t.t()
+    return t.contiguous()
+
+
+class System:
+    """One or more replicas resident on one GPU behind a libvbc handle."""
+
+    def __init__(self, reps, precision="fp64", k_max=0, brick=0, block=0, stage_cap=0,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        if isinstance(reps, dict):
+            reps = [reps]
+        self.reps = reps
+        self.nrep = len(reps)
+        self.ntot = sum(r["n"] for r in reps)
+        self.offsets = np.concatenate([[0], np.cumsum([r["n"] for r in reps])]).astype(np.int64)
+        self.device = torch.device(device)
+        arr, keep = _descs(reps)
+        o = _options(precision, k_max, brick, block, stage_cap)
+        n = C.c_size_t(0)
+        _check(lib().vbc_workspace_size(arr, self.nrep, C.byref(o), C.byref(n)))
+        self.ws_bytes = int(n.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        h = C.c_void_p()
+        _check(lib().vbc_create(arr, self.nrep, C.byref(o), C.c_void_p(self._ws_ptr),
+                                C.c_size_t(self.ws_bytes), self._stream(), C.byref(h)))
+        self.h = h
+        self.precision = precision
+
+    # -- plumbing -----------------------------------------------------------
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _ok(self, st):
+        _check(st, self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vbc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def options(self):
+        o = Options()
+        self._ok(lib().vbc_get_options(self.h, C.byref(o)))
+        return dict(precision=o.precision, k_max=o.k_max, brick=o.brick, block=o.block,
+                    stage_cap=o.stage_cap)
+
+    # -- state --------------------------------------------------------------
+    def set_state(self, x, v=None, types=None, rep=-1, step0=0):
+        torch = self.torch
+        n = self.ntot if rep < 0 else self.reps[rep]["n"]
+        xs = _soa(x, n, torch, self.device, torch.float64)
+        vs = _soa(v, n, torch, self.device, torch.float64) if v is not None else None
+        ts = None
+        if types is not None:
+            ts = (torch.from_numpy(np.ascontiguousarray(types)) if isinstance(types, np.ndarray)
+                  else types).to(device=self.device, dtype=torch.int32).contiguous()
+        self._ok(lib().vbc_set_state(self.h, rep, _ptr(xs), _ptr(vs), _ptr(ts), int(step0),
+                                     self._stream()))
+        self._keep = (xs, vs, ts)  # alive until the copy kernel has run
+
+    def get_state(self, rep=-1):
+        torch = self.torch
+        n = self.ntot if rep < 0 else self.reps[rep]["n"]
+        x = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        v = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        self._ok(lib().vbc_get_state(self.h, rep, _ptr(x), _ptr(v), self._stream()))
+        return x.t(), v.t()
+
+    # -- the hot path -------------------------------------------------------
+    def build_nlist(self):
+        self._ok(lib().vbc_build_nlist(self.h, self._stream()))
+
+    def count(self):
+        n = self.torch.empty(self.ntot, dtype=self.torch.float64, device=self.device)
+        self._ok(lib().vbc_count(self.h, _ptr(n), self._stream()))
+        return n
+
+    def force(self, energies=True):
+        torch = self.torch
+        F = torch.empty((3, self.ntot), dtype=torch.float64, device=self.device)
+        e = torch.empty(self.ntot, dtype=torch.float64, device=self.device) if energies else None
+        UW = torch.empty((self.nrep, 8), dtype=torch.float64, device=self.device) if energies else None
+        self._ok(lib().vbc_force(self.h, _ptr(F), _ptr(e), _ptr(UW), self._stream()))
+        return F.t(), e, UW
+
+    def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
+        it = Integrator()
+        it.kind = NVE if integrator in ("nve", NVE) else LANGEVIN
+        it.dt, it.kT, it.gamma, it.seed = float(dt), float(kT), float(gamma), int(seed)
+        self._ok(lib().vbc_step(self.h, int(nsteps), C.byref(it), self._stream()))
+
+    def check(self, raise_on_error=True):
+        flags = (C.c_uint32 * self.nrep)()
+        st = lib().vbc_check(self.h, self._stream(), flags)
+        if raise_on_error:
+            self._ok(st)
+        return st, [int(f) for f in flags]
+
+    def nlist_pairs(self, rep=0, cap=None):
+        torch = self.torch
+        n = self.reps[rep]["n"]
+        if cap is None:
+            cap = n * self.options()["k_max"]
+        pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self._ok(lib().vbc_get_nlist(self.h, rep, _ptr(pairs), int(cap), _ptr(cnt), self._stream()))
+        c = int(cnt.item())
+        return pairs[: min(c, cap)].cpu().numpy(), c
