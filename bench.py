@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the VBC hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--f 4] [--no-sweep] [--no-cpu]
+
+Workload (default): N = 1,000,000 particles, cubic periodic box at number density 0.5,
+uniform random start, standard VBC(1.5, 2.0, 0) on the polynomial soft core (E_r = 20,
+r_r = 1, r_a = 1.5), well depth 5 kT, valency 4, list buffer 0.4; FP32 pair arithmetic
+with FP64 counts, switching, integration and reductions; Langevin (BAOAB) kT = 1,
+gamma = 0.1, dt = 0.005.  A step is one whole timestep of the hot path: list rebuild when
+due, count pass, sparse dU/dn pass, force pass with the fused integrator update.
+
+Prints ONE JSON line.  `value` is pair evaluations per second (ordered pairs inside the
+interaction cutoff handled per step, times steps per second); timesteps/s is reported
+beside it.  `roofline` is the dominant kernel's algorithmic bytes per launch over its
+mean duration, timed with HIP events on the launch stream inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "VBC pair evals/s + timesteps/s at N=1M (frac. HBM roofline); p99 step latency batched"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(kind: str, N: int, kbar: float, precision: str) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel class, for the chosen layout.
+
+    Every datum a launch needs is counted once: list entries are 2 bytes, counts per
+    particle 2 bytes, positions/velocities/reference positions FP64 SoA; halo copies
+    staged by several workgroups are cache re-reads, not algorithmic traffic."""
+    sa = 8 if precision == "fp32" else 16
+    if kind == "count":
+        # list + nn + x + type  ->  n (FP64) + (s, A)
+        return N * (2 * kbar + 2 + 24 + 4 + 8 + sa)
+    if kind == "force":
+        # list + nn + x + type + (s, A) + tag + v (r/w) + x_next (w) + x_ref (r)
+        return N * (2 * kbar + 2 + 24 + 4 + sa + 4 + 48 + 24 + 24)
+    if kind == "build":
+        # x, v, tag, type read and gathered, cell tables, list written
+        return N * (48 + 8 + 4 * 6 + 48 + 8 + 24 + 2 * kbar + 2)
+    return float("nan")
+
+
+def cpu_baseline(wl, target_s=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: full VBC forces of m
+    particles of the N = 10^6 configuration (each needs O(N) scans for its own and its
+    neighbours' counts).  Returns pair evaluations delivered per second."""
+    import oracle
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(123)
+    rc = max(wl.params["r_r"], wl.params["r_a"], wl.params["r_h"])
+    tree = cKDTree(wl.x, boxsize=wl.L)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on one batch of `cores` particles, then size the measured sample
+    idx = rng.choice(wl.N, size=cores, replace=False)
+    t0 = time.perf_counter()
+    oracle.evaluate_subset(wl.x, wl.L, wl.params, idx)
+    t_cal = time.perf_counter() - t0
+    m = int(max(cores, min(4096, cores * max(1, round(target_s / max(t_cal, 1e-3))))))
+    idx = rng.choice(wl.N, size=m, replace=False)
+    t0 = time.perf_counter()
+    oracle.evaluate_subset(wl.x, wl.L, wl.params, idx)
+    dt = time.perf_counter() - t0
+    pairs = sum(len(v) - 1 for v in tree.query_ball_point(wl.x[idx], rc))
+    return {"value": pairs / dt, "unit": "pair evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m} particles of the N={wl.N} start configuration: FP64 forces by the "
+                      f"O(N^2) oracle ({pairs} pair evaluations in {dt:.1f} s)",
+            "seconds": dt}
+
+
+def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True):
+    wl = W.headline(f=f, seed=seed)
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32")
+    s.set_state(wl.x, wl.v)
+    integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=seed)
+    # warmup: relax the random start and reach a steady rebuild rate
+    done = 0
+    while done < warmup:
+        k = min(500, warmup - done)
+        s.step(k, **integ)
+        done += k
+    s.check()
+    st0 = s.stats()[0]
+    if profile:
+        s.profile(True, max_launches=steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, **integ)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read() if profile else None
+    s.check()
+    st1 = s.stats()[0]
+    elapsed = t1 - t0
+    evals = st1["evals"] - st0["evals"]
+    pair_evals = (st1["pair_evals"] - st0["pair_evals"]) / max(evals, 1)
+    builds = st1["builds"] - st0["builds"]
+    kbar = st1["list_entries"] / wl.N
+    out = dict(wl=wl, elapsed=elapsed, pair_evals_per_step=pair_evals, builds=builds, kbar=kbar,
+               prof=prof, opts=s.options())
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--f", type=float, default=4.0)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus}, WORLD_SIZE={world} requested); "
+              "this build runs each system on a single MI355X and has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_07842_amd import vbc
+    from paper_2609_07842_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    main_run = run_one(W, vbc, torch, args.f, args.steps, args.warmup, args.seed)
+    wl = main_run["wl"]
+    K = args.steps
+    tsps = K / main_run["elapsed"]
+    pe_step = main_run["pair_evals_per_step"]
+    prof = main_run["prof"]
+    kernels = {k: {"mean_us": 1e3 * ms / n if n else None, "launches": n, "total_ms": ms}
+               for k, (ms, n) in prof.items()}
+    dom = max(("build", "count", "embed", "force"), key=lambda k: prof[k][0])
+    ms, n = prof[dom]
+    mean_s = ms / n / 1e3
+    nbytes = kernel_bytes(dom, wl.N, main_run["kbar"], "fp32")
+    achieved = nbytes / mean_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": nbytes, "mean_launch_us": mean_s * 1e6}
+    # whole-step view: all kernels' algorithmic bytes per step over the step time
+    step_bytes = (kernel_bytes("count", wl.N, main_run["kbar"], "fp32")
+                  + kernel_bytes("force", wl.N, main_run["kbar"], "fp32")
+                  + kernel_bytes("build", wl.N, main_run["kbar"], "fp32") * main_run["builds"] / K)
+
+    sweep = None
+    if not args.no_sweep:
+        sweep = {}
+        for f in (1, 2, 3, 4, 5, 6):
+            r = run_one(W, vbc, torch, float(f), max(200, K // 2), max(500, args.warmup // 2),
+                        args.seed, profile=False)
+            ts = max(200, K // 2) / r["elapsed"]
+            sweep[str(f)] = {"timesteps_per_s": ts, "pair_evals_per_s": ts * r["pair_evals_per_step"],
+                             "builds": r["builds"]}
+        vals = [v["timesteps_per_s"] for v in sweep.values()]
+        sweep["flatness_max_over_min"] = max(vals) / min(vals)
+
+    cpu = None if args.no_cpu else cpu_baseline(wl)
+
+    line = {
+        "metric": METRIC,
+        "value": tsps * pe_step,
+        "unit": "pair evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_run["elapsed"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 counts/switching/integration/reductions",
+        "data": "synthetic",
+        "config": {"workload": "N=1,000,000 uniform-random start, density 0.5, valency 4, "
+                               "eps=5kT, standard VBC(1.5,2.0,0), skin 0.4, Langevin kT=1 "
+                               "gamma=0.1 dt=0.005",
+                   "N": wl.N, "rho": 0.5, "f": args.f, "E_a": 5.0, "precision": "fp32_mixed",
+                   "parallelism": "single GPU"},
+        "timesteps_per_s": tsps,
+        "particle_steps_per_s": tsps * wl.N,
+        "pair_evals_per_step": pe_step,
+        "list_entries_per_particle": main_run["kbar"],
+        "steps_per_rebuild": K / max(main_run["builds"], 1),
+        "layout": main_run["opts"],
+        "kernels": kernels,
+        "step_model_GBs": step_bytes * tsps / 1e9,
+        "roofline": roofline,
+        "f_sweep": sweep,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,9 @@ enum {
     VBC_FLAG_REBUILD = 1u,         /* internal: list rebuild pending */
     VBC_FLAG_NLIST_OVERFLOW = 2u,
     VBC_FLAG_STAGE_OVERFLOW = 4u,
-    VBC_FLAG_NONFINITE = 8u
+    VBC_FLAG_NONFINITE = 8u,
+    VBC_FLAG_LOST = 16u            /* a particle moved further than one cell between two list
+                                      builds (unstable dynamics); reported as VBC_ERR_NONFINITE */
 };
 
 /* Parameters of one type pair (Section 2, eq. (softcore); eq. (counter); eq. (Psidelta)).
@@ -171,6 +173,26 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
 
 /* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
 vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
+
+/* Counters kept per replica on the GPU (read with vbc_get_stats, which synchronises s):
+ * list builds so far, list entries after the last build (sum over particles), ordered
+ * pairs inside the interaction cutoff summed over all count passes, and the number of
+ * count passes.  pair_evals / evals is the mean number of pair evaluations per pass. */
+typedef struct {
+    uint64_t builds, list_entries, pair_evals, evals;
+} vbc_stats;
+vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out /* host [nrep] */);
+
+/* Kernel timing with HIP events recorded on the launch stream around every launch of each
+ * kernel class, for at most max_launches launches per class (enable = 0 switches it off).
+ * Classes: 0 list build (its five kernels together), 1 count, 2 embed, 3 force,
+ * 4 first-step kick, 5 reductions.  vbc_profile_read synchronises s and returns, per
+ * class, the summed milliseconds and the number of timed launches, then resets them. */
+enum { VBC_K_BUILD = 0, VBC_K_COUNT = 1, VBC_K_EMBED = 2, VBC_K_FORCE = 3, VBC_K_KICK = 4,
+       VBC_K_REDUCE = 5, VBC_NK = 6 };
+vbc_status vbc_profile(vbc_handle h, int32_t enable, int32_t max_launches);
+vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms /* [VBC_NK] */,
+                            int64_t *launches /* [VBC_NK] */);
 
 #ifdef __cplusplus
 }

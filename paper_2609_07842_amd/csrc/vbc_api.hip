@@ -19,11 +19,41 @@ struct vbc_handle_s {
     Buffers B;
     std::vector<RepDev> reps;
     vbc_options opt;
-    int cur = 0;          // which position buffer holds the current positions
-    bool f_valid = false; // Fst holds the forces of the current positions
+    int cur = 0;            // which position buffer holds the current positions
+    bool f_valid = false;   // Fst holds the forces of the current positions
     bool have_state = false;
+    bool need_full = false; // unsorted input waiting for a full build
     std::string err;
+    // kernel timing (vbc_profile)
+    bool prof = false;
+    int prof_max = 0;
+    std::vector<hipEvent_t> ev[VBC_NK][2];
+    int prof_n[VBC_NK] = {0, 0, 0, 0, 0, 0};
+    ~vbc_handle_s()
+    {
+        for (int k = 0; k < VBC_NK; ++k)
+            for (int e = 0; e < 2; ++e)
+                for (hipEvent_t x : ev[k][e]) (void)hipEventDestroy(x);
+    }
 };
+
+// Record the launch(es) of one kernel class between two events when timing is on.
+template <class Fn>
+static hipError_t timed(vbc_handle h, int kind, hipStream_t s, Fn &&fn)
+{
+    bool on = h->prof && h->prof_n[kind] < h->prof_max;
+    if (on) {
+        hipError_t e = hipEventRecord(h->ev[kind][0][h->prof_n[kind]], s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = fn();
+    if (e != hipSuccess) return e;
+    if (on) {
+        e = hipEventRecord(h->ev[kind][1][h->prof_n[kind]], s);
+        h->prof_n[kind]++;
+    }
+    return e;
+}
 
 namespace {
 
@@ -36,9 +66,10 @@ struct Layout {
     vbc_options opt;
     size_t bytes = 0;
     // byte offsets into the workspace
-    size_t o_reps, o_cell_rank, o_brick_rank0, o_cell_cnt, o_cell_start, o_x0, o_x1, o_v, o_Fst,
-        o_xref, o_tag, o_type, o_pcell, o_inv, o_slot, o_perm, o_xs, o_vs, o_tags, o_types,
-        o_pcs, o_nl, o_nn, o_nd, o_sA, o_win, o_part, o_flags, o_step;
+    size_t o_reps, o_cell_rank, o_brick_rank0, o_cstart0, o_cstart1, o_ccnt0, o_ccnt1, o_bcnt0,
+        o_bcnt1, o_bfill, o_x0, o_x1, o_v, o_Fst, o_xref, o_tag, o_type, o_lcell, o_xs, o_vs,
+        o_tags, o_types, o_lcells, o_src, o_inv, o_nl, o_nn, o_nd, o_sA, o_win, o_part, o_flags,
+        o_step, o_stats, o_bevals, o_bentries;
 };
 
 vbc_status fail(vbc_status st, const std::string &msg)
@@ -102,6 +133,8 @@ size_t carve(size_t &off, size_t bytes)
     return o;
 }
 
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
 vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in, Layout &Lo)
 {
     if (!reps || nrep < 1) return fail(VBC_ERR_ARG, "need at least one replica");
@@ -113,7 +146,7 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
     if (opt.brick < 0 || opt.brick > MAX_BRICK) return fail(VBC_ERR_ARG, "brick must be 0..6");
     if (opt.block != 0 && (opt.block < 64 || opt.block > 1024 || opt.block % 64))
         return fail(VBC_ERR_ARG, "block must be a multiple of 64 in 64..1024");
-    if (opt.k_max < 0 || opt.k_max > 65535) return fail(VBC_ERR_ARG, "k_max must be 0..65535");
+    if (opt.k_max < 0 || opt.k_max > 65528) return fail(VBC_ERR_ARG, "k_max must be 0..65528");
     if (opt.stage_cap < 0 || opt.stage_cap > 65535)
         return fail(VBC_ERR_ARG, "stage_cap must be 0..65535");
 
@@ -122,10 +155,10 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
     P.nrep = nrep;
     P.precision = opt.precision;
     int brick_target = opt.brick ? opt.brick : (opt.precision == VBC_FP64 ? 3 : 4);
-    double rho_cell_max = 0.0, k_mean_max = 0.0;
-    int64_t p_off = 0;
-    int32_t c_off = 0, cs_off = 0, b_off = 0;
-    int nh_max = 1, ntypes_max = 1, any_chains = 0;
+    double rho_cell_max = 0.0, k_mean_max = 0.0, own_mean_max = 0.0;
+    int64_t p_off = 0, o_off = 0;
+    int32_t c_off = 0, b_off = 0;
+    int nh_max = 1, ntypes_max = 1, any_chains = 0, bcap_max = 0, ncb_max = 1;
     Lo.reps.resize(nrep);
     for (int r = 0; r < nrep; ++r) {
         const vbc_replica_desc &d = reps[r];
@@ -186,20 +219,29 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
         }
         R.k_bond = d.k_bond;
         R.r0_bond = d.r0_bond;
+        // slots per brick: the mean occupancy of a full brick with room for fluctuations
+        int ncb_full = R.bd[0] * R.bd[1] * R.bd[2];
+        double per_cell = (double)d.n / (double)ncell;
+        double own_mean = per_cell * ncb_full;
+        R.bcap = std::min((int64_t)round_up((int)std::ceil(own_mean * 1.4 + 64.0), 64),
+                          std::max<int64_t>(64, d.n));
+        if ((int64_t)R.bcap * R.nbrick < d.n) R.bcap = (int32_t)((d.n + R.nbrick - 1) / R.nbrick);
         R.p_off = p_off;
-        R.o_off = p_off;
+        R.o_off = o_off;
         R.n = d.n;
         R.c_off = c_off;
-        R.cs_off = cs_off;
         R.b_off = b_off;
-        p_off += d.n;
+        p_off += (int64_t)R.nbrick * R.bcap;
+        o_off += d.n;
         c_off += R.ncell;
-        cs_off += R.ncell + 1;
         b_off += R.nbrick;
         nh_max = std::max(nh_max, (R.bd[0] + 2) * (R.bd[1] + 2) * (R.bd[2] + 2));
+        ncb_max = std::max(ncb_max, ncb_full);
+        bcap_max = std::max(bcap_max, (int)R.bcap);
         ntypes_max = std::max(ntypes_max, (int)d.ntypes);
         double vol = d.L[0] * d.L[1] * d.L[2];
-        rho_cell_max = std::max(rho_cell_max, (double)d.n / (double)ncell);
+        rho_cell_max = std::max(rho_cell_max, per_cell);
+        own_mean_max = std::max(own_mean_max, own_mean);
         k_mean_max = std::max(k_mean_max, (double)d.n / vol * 4.18879020478639 * rl * rl * rl);
         // static tables: brick-major ranks (x fastest inside a brick and across bricks)
         size_t base = Lo.cell_rank.size();
@@ -221,22 +263,26 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
                 }
         Lo.reps[r] = R;
     }
-    if (p_off >= ((int64_t)1 << 31)) return fail(VBC_ERR_ARG, "more than 2^31 particles in total");
-    P.ntot = p_off;
+    if (p_off >= ((int64_t)1 << 31) - 1) return fail(VBC_ERR_ARG, "more than 2^31 slots in total");
+    P.ntot = o_off;
+    P.nslots = p_off;
     P.ncell_tot = c_off;
-    P.ncs_tot = cs_off;
     P.nbrick_tot = b_off;
     P.nh_max = nh_max;
+    P.ncb_max = ncb_max;
+    P.bcap_max = bcap_max;
     P.ntypes_max = ntypes_max;
     P.any_chains = any_chains;
-    P.block = opt.block ? opt.block : 256;
-    P.k_max = opt.k_max ? opt.k_max : std::min(65535, ((int)std::ceil(k_mean_max * 1.6 + 24.0) + 7) / 8 * 8);
+    P.block = opt.block ? opt.block
+                        : std::max(128, std::min(512, round_up((int)std::ceil(own_mean_max), 64)));
+    P.k_max = opt.k_max ? round_up(opt.k_max, CHUNK)
+                        : std::min(65528, round_up((int)std::ceil(k_mean_max * 1.6 + 24.0), CHUNK));
+    P.nchunk = P.k_max / CHUNK;
     if (opt.stage_cap) {
         P.stage_cap = opt.stage_cap;
     } else {
         double mean = rho_cell_max * nh_max;
-        int cap = ((int)std::ceil(mean * 1.5 + 64.0) + 63) / 64 * 64;
-        P.stage_cap = std::min(65535, cap);
+        P.stage_cap = std::min(65535, round_up((int)std::ceil(mean * 1.3 + 96.0), 32));
     }
     opt.k_max = P.k_max;
     opt.block = P.block;
@@ -246,36 +292,43 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
 
     // workspace
     size_t off = 0;
-    const int64_t n = P.ntot;
+    const int64_t S = P.nslots;
     Lo.o_reps = carve(off, sizeof(RepDev) * nrep);
     Lo.o_cell_rank = carve(off, sizeof(int32_t) * P.ncell_tot);
     Lo.o_brick_rank0 = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_cell_cnt = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_cell_start = carve(off, sizeof(int64_t) * P.ncs_tot);
-    Lo.o_x0 = carve(off, sizeof(double) * 3 * n);
-    Lo.o_x1 = carve(off, sizeof(double) * 3 * n);
-    Lo.o_v = carve(off, sizeof(double) * 3 * n);
-    Lo.o_Fst = carve(off, sizeof(double) * 3 * n);
-    Lo.o_xref = carve(off, sizeof(double) * 3 * n);
-    Lo.o_tag = carve(off, sizeof(int32_t) * n);
-    Lo.o_type = carve(off, sizeof(int32_t) * n);
-    Lo.o_pcell = carve(off, sizeof(int32_t) * n);
-    Lo.o_inv = carve(off, sizeof(int64_t) * n);
-    Lo.o_slot = carve(off, sizeof(int32_t) * n);
-    Lo.o_perm = carve(off, sizeof(int32_t) * n);
-    Lo.o_xs = carve(off, sizeof(double) * 3 * n);
-    Lo.o_vs = carve(off, sizeof(double) * 3 * n);
-    Lo.o_tags = carve(off, sizeof(int32_t) * n);
-    Lo.o_types = carve(off, sizeof(int32_t) * n);
-    Lo.o_pcs = carve(off, sizeof(int32_t) * n);
-    Lo.o_nl = carve(off, sizeof(uint16_t) * (size_t)P.k_max * n);
-    Lo.o_nn = carve(off, sizeof(uint16_t) * n);
-    Lo.o_nd = carve(off, sizeof(double) * n);
-    Lo.o_sA = carve(off, (P.precision == VBC_FP64 ? 16 : 8) * (size_t)n);
+    Lo.o_cstart0 = carve(off, sizeof(int32_t) * P.ncell_tot);
+    Lo.o_cstart1 = carve(off, sizeof(int32_t) * P.ncell_tot);
+    Lo.o_ccnt0 = carve(off, sizeof(int32_t) * P.ncell_tot);
+    Lo.o_ccnt1 = carve(off, sizeof(int32_t) * P.ncell_tot);
+    Lo.o_bcnt0 = carve(off, sizeof(int32_t) * P.nbrick_tot);
+    Lo.o_bcnt1 = carve(off, sizeof(int32_t) * P.nbrick_tot);
+    Lo.o_bfill = carve(off, sizeof(int32_t) * P.nbrick_tot);
+    Lo.o_x0 = carve(off, sizeof(double) * 3 * S);
+    Lo.o_x1 = carve(off, sizeof(double) * 3 * S);
+    Lo.o_v = carve(off, sizeof(double) * 3 * S);
+    Lo.o_Fst = carve(off, sizeof(double) * 3 * S);
+    Lo.o_xref = carve(off, sizeof(double) * 3 * S);
+    Lo.o_tag = carve(off, sizeof(int32_t) * S);
+    Lo.o_type = carve(off, sizeof(int32_t) * S);
+    Lo.o_lcell = carve(off, S);
+    Lo.o_xs = carve(off, sizeof(double) * 3 * S);
+    Lo.o_vs = carve(off, sizeof(double) * 3 * S);
+    Lo.o_tags = carve(off, sizeof(int32_t) * S);
+    Lo.o_types = carve(off, sizeof(int32_t) * S);
+    Lo.o_lcells = carve(off, S);
+    Lo.o_src = carve(off, sizeof(int32_t) * S);
+    Lo.o_inv = carve(off, sizeof(int32_t) * P.ntot);
+    Lo.o_nl = carve(off, 16 * (size_t)P.nchunk * S);
+    Lo.o_nn = carve(off, sizeof(uint16_t) * S);
+    Lo.o_nd = carve(off, sizeof(double) * S);
+    Lo.o_sA = carve(off, (P.precision == VBC_FP64 ? 16 : 8) * (size_t)S);
     Lo.o_win = carve(off, P.nbrick_tot);
     Lo.o_part = carve(off, sizeof(double) * 8 * (size_t)P.nbrick_tot);
     Lo.o_flags = carve(off, sizeof(uint32_t) * nrep);
     Lo.o_step = carve(off, sizeof(uint64_t) * nrep);
+    Lo.o_stats = carve(off, sizeof(unsigned long long) * 4 * nrep);
+    Lo.o_bevals = carve(off, sizeof(unsigned long long) * P.nbrick_tot);
+    Lo.o_bentries = carve(off, sizeof(uint32_t) * P.nbrick_tot);
     Lo.bytes = off;
     return VBC_OK;
 }
@@ -290,13 +343,31 @@ vbc_status hip_fail(vbc_handle h, hipError_t e, const char *where)
     return VBC_ERR_HIP;
 }
 
-#define VBC_TRY(h, expr, where)                        \
-    do {                                               \
-        hipError_t _e = (expr);                        \
-        if (_e != hipSuccess) return hip_fail(h, _e, where); \
+#define VBC_TRY(h, expr, where)                                  \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return hip_fail(h, _e, where);     \
     } while (0)
 
 }  // namespace
+
+// The first build after vbc_set_state starts from caller-order input.
+static vbc_status ensure_layout(vbc_handle h, hipStream_t s)
+{
+    if (!h->need_full) return VBC_OK;
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_full_build(h->B, h->P, h->cur, s); }),
+            "full build");
+    VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD | FLAG_FULL, false, s), "flags");
+    h->need_full = false;
+    h->f_valid = false;
+    return VBC_OK;
+}
+
+#define VBC_LAYOUT(h, s)                          \
+    do {                                          \
+        vbc_status _st = ensure_layout(h, s);     \
+        if (_st != VBC_OK) return _st;            \
+    } while (0)
 
 extern "C" {
 
@@ -330,7 +401,8 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
     e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
     size_t need = std::max(std::max(lds_bytes_nlist(Lo.P), lds_bytes_count(Lo.P)),
-                           std::max(lds_bytes_embed(Lo.P), lds_bytes_force(Lo.P)));
+                           std::max(std::max(lds_bytes_embed(Lo.P), lds_bytes_force(Lo.P)),
+                                    lds_bytes_sort(Lo.P)));
     if (need + 2048 > (size_t)lds_max)
         return fail(VBC_ERR_CAPACITY, "staging needs " + std::to_string(need) +
                                           " bytes of LDS per workgroup; the device allows " +
@@ -345,8 +417,13 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
     B.reps = at<RepDev>(d_ws, Lo.o_reps);
     B.cell_rank = at<int32_t>(d_ws, Lo.o_cell_rank);
     B.brick_rank0 = at<int32_t>(d_ws, Lo.o_brick_rank0);
-    B.cell_cnt = at<int32_t>(d_ws, Lo.o_cell_cnt);
-    B.cell_start = at<int64_t>(d_ws, Lo.o_cell_start);
+    B.cstart[0] = at<int32_t>(d_ws, Lo.o_cstart0);
+    B.cstart[1] = at<int32_t>(d_ws, Lo.o_cstart1);
+    B.ccnt[0] = at<int32_t>(d_ws, Lo.o_ccnt0);
+    B.ccnt[1] = at<int32_t>(d_ws, Lo.o_ccnt1);
+    B.bcnt[0] = at<int32_t>(d_ws, Lo.o_bcnt0);
+    B.bcnt[1] = at<int32_t>(d_ws, Lo.o_bcnt1);
+    B.bfill = at<int32_t>(d_ws, Lo.o_bfill);
     B.x[0] = at<double>(d_ws, Lo.o_x0);
     B.x[1] = at<double>(d_ws, Lo.o_x1);
     B.v = at<double>(d_ws, Lo.o_v);
@@ -354,16 +431,15 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
     B.xref = at<double>(d_ws, Lo.o_xref);
     B.tag = at<int32_t>(d_ws, Lo.o_tag);
     B.type = at<int32_t>(d_ws, Lo.o_type);
-    B.pcell = at<int32_t>(d_ws, Lo.o_pcell);
-    B.inv = at<int64_t>(d_ws, Lo.o_inv);
-    B.slot = at<int32_t>(d_ws, Lo.o_slot);
-    B.perm = at<int32_t>(d_ws, Lo.o_perm);
+    B.lcell = at<uint8_t>(d_ws, Lo.o_lcell);
     B.xs = at<double>(d_ws, Lo.o_xs);
     B.vs = at<double>(d_ws, Lo.o_vs);
     B.tags = at<int32_t>(d_ws, Lo.o_tags);
     B.types = at<int32_t>(d_ws, Lo.o_types);
-    B.pcs = at<int32_t>(d_ws, Lo.o_pcs);
-    B.nl = at<uint16_t>(d_ws, Lo.o_nl);
+    B.lcells = at<uint8_t>(d_ws, Lo.o_lcells);
+    B.src = at<int32_t>(d_ws, Lo.o_src);
+    B.inv = at<int32_t>(d_ws, Lo.o_inv);
+    B.nl = at<uint4>(d_ws, Lo.o_nl);
     B.nn = at<uint16_t>(d_ws, Lo.o_nn);
     B.nd = at<double>(d_ws, Lo.o_nd);
     B.sA = at<void>(d_ws, Lo.o_sA);
@@ -371,8 +447,11 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
     B.part = at<double>(d_ws, Lo.o_part);
     B.flags = at<uint32_t>(d_ws, Lo.o_flags);
     B.step = at<uint64_t>(d_ws, Lo.o_step);
+    B.stats = at<unsigned long long>(d_ws, Lo.o_stats);
+    B.bevals = at<unsigned long long>(d_ws, Lo.o_bevals);
+    B.bentries = at<uint32_t>(d_ws, Lo.o_bentries);
 
-    // static tables; everything else starts at zero
+    // static tables; everything else starts at zero (no particle in any brick)
     e = hipMemsetAsync(d_ws, 0, Lo.bytes, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B.reps, Lo.reps.data(), sizeof(RepDev) * nrep, hipMemcpyHostToDevice, s);
@@ -411,49 +490,41 @@ vbc_status vbc_get_options(vbc_handle h, vbc_options *out)
     return VBC_OK;
 }
 
-static bool rep_range(vbc_handle h, int32_t rep, int &lo, int &hi, int64_t &n, int64_t &off)
-{
-    if (rep < 0) {
-        lo = 0;
-        hi = h->P.nrep - 1;
-        n = h->P.ntot;
-        off = 0;
-        return true;
-    }
-    if (rep >= h->P.nrep) return false;
-    lo = hi = rep;
-    n = h->reps[rep].n;
-    off = h->reps[rep].o_off;
-    return true;
-}
-
 vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const double *d_v,
                          const int32_t *d_type, uint64_t step0, hipStream_t s)
 {
     if (!h || !d_x) return fail(VBC_ERR_ARG, "NULL argument");
-    int lo, hi;
-    int64_t n, off;
-    if (!rep_range(h, rep, lo, hi, n, off)) {
+    if (rep >= h->P.nrep) {
         h->err = "replica index out of range";
         return VBC_ERR_ARG;
     }
-    VBC_TRY(h, launch_set_state(h->B, h->P, lo, hi, d_x, d_v, d_type, step0, s, n, off), "set_state");
-    // both position buffers were written: either may serve as current
+    // a pending full build of other replicas must not see this one half-written
+    int64_t n = rep < 0 ? h->P.ntot : h->reps[rep].n;
+    int64_t off = rep < 0 ? 0 : h->reps[rep].o_off;
+    VBC_TRY(h, launch_set_state(h->B, h->P, h->cur, d_x, d_v, d_type, step0, s, n, off), "set_state");
     h->f_valid = false;
     h->have_state = true;
+    h->need_full = true;
     return VBC_OK;
 }
 
 vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    int lo, hi;
-    int64_t n, off;
-    if (!rep_range(h, rep, lo, hi, n, off)) {
+    if (rep >= h->P.nrep) {
         h->err = "replica index out of range";
         return VBC_ERR_ARG;
     }
-    VBC_TRY(h, launch_get_state(h->B, h->P, h->cur, lo, hi, d_x, d_v, s, n, off), "get_state");
+    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    VBC_LAYOUT(h, s);
+    int lo = rep < 0 ? 0 : rep, hi = rep < 0 ? h->P.nrep - 1 : rep;
+    int64_t slot_lo = h->reps[lo].p_off;
+    int64_t slot_hi = h->reps[hi].p_off + (int64_t)h->reps[hi].nbrick * h->reps[hi].bcap;
+    int64_t out_off = h->reps[lo].o_off;
+    int64_t out_stride = rep < 0 ? h->P.ntot : h->reps[rep].n;
+    VBC_TRY(h, launch_get_state(h->B, h->P, h->cur, slot_lo, slot_hi - slot_lo, out_off, out_stride,
+                                d_x, d_v, s),
+            "get_state");
     return VBC_OK;
 }
 
@@ -461,8 +532,12 @@ vbc_status vbc_build_nlist(vbc_handle h, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    if (h->need_full) {
+        VBC_LAYOUT(h, s);
+        return VBC_OK;
+    }
     VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD, true, s), "flags");
-    VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
     VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD, false, s), "flags");
     h->f_valid = false;
     return VBC_OK;
@@ -472,9 +547,9 @@ vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
-    VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
-    VBC_TRY(h, launch_count(h->B, h->P, h->cur, d_n, s), "count");
-    h->f_valid = false;
+    VBC_LAYOUT(h, s);
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, s); }), "count");
     return VBC_OK;
 }
 
@@ -485,16 +560,31 @@ static StepArgs no_step()
     return st;
 }
 
+// count, embed and force of the current positions into Fst (and the optional outputs)
+static vbc_status eval_forces(vbc_handle h, bool thermo, const StepArgs &st, double *d_F, double *d_e,
+                              hipStream_t s)
+{
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
+    VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
+                return launch_force(h->B, h->P, h->cur, MODE_EVAL, thermo, st, d_F, d_e, s);
+            }),
+            "force");
+    return VBC_OK;
+}
+
 vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    VBC_LAYOUT(h, s);
     bool thermo = d_e || d_UW;
-    VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
-    VBC_TRY(h, launch_count(h->B, h->P, h->cur, nullptr, s), "count");
-    VBC_TRY(h, launch_embed(h->B, h->P, h->cur, s), "embed");
-    VBC_TRY(h, launch_force(h->B, h->P, h->cur, MODE_EVAL, thermo, no_step(), d_F, d_e, s), "force");
-    if (d_UW) VBC_TRY(h, launch_reduce(h->B, h->P, d_UW, s), "reduce");
+    vbc_status st = eval_forces(h, thermo, no_step(), d_F, d_e, s);
+    if (st != VBC_OK) return st;
+    if (d_UW)
+        VBC_TRY(h, timed(h, VBC_K_REDUCE, s, [&] { return launch_reduce(h->B, h->P, d_UW, s); }),
+                "reduce");
     h->f_valid = true;
     return VBC_OK;
 }
@@ -511,6 +601,7 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
         return VBC_ERR_ARG;
     }
     if (nsteps == 0) return VBC_OK;
+    VBC_LAYOUT(h, s);
     StepArgs st = no_step();
     st.kind = it->kind;
     st.dt = it->dt;
@@ -520,22 +611,22 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
     st.c2s = std::sqrt(1.0 - st.c1 * st.c1) * std::sqrt(it->kT);
     st.seed = it->seed;
     if (!h->f_valid) {
-        VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
-        VBC_TRY(h, launch_count(h->B, h->P, h->cur, nullptr, s), "count");
-        VBC_TRY(h, launch_embed(h->B, h->P, h->cur, s), "embed");
-        VBC_TRY(h, launch_force(h->B, h->P, h->cur, MODE_EVAL, false, st, nullptr, nullptr, s), "force");
+        vbc_status r = eval_forces(h, false, st, nullptr, nullptr, s);
+        if (r != VBC_OK) return r;
     }
     st.step_off = 0;
-    VBC_TRY(h, launch_kick_drift(h->B, h->P, h->cur, st, s), "kick");
+    VBC_TRY(h, timed(h, VBC_K_KICK, s, [&] { return launch_kick_drift(h->B, h->P, h->cur, st, s); }), "kick");
     h->cur ^= 1;
     for (int k = 0; k < nsteps; ++k) {
-        VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
-        VBC_TRY(h, launch_count(h->B, h->P, h->cur, nullptr, s), "count");
-        VBC_TRY(h, launch_embed(h->B, h->P, h->cur, s), "embed");
+        VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+        VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, s); }), "count");
+        VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
         bool last = (k == nsteps - 1);
         st.step_off = (uint64_t)k + 1;
-        VBC_TRY(h, launch_force(h->B, h->P, h->cur, last ? MODE_LAST : MODE_MID, false, st, nullptr,
-                                nullptr, s),
+        VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
+                    return launch_force(h->B, h->P, h->cur, last ? MODE_LAST : MODE_MID, false, st,
+                                        nullptr, nullptr, s);
+                }),
                 "force");
         if (!last) h->cur ^= 1;
     }
@@ -551,21 +642,27 @@ vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica)
     std::vector<uint32_t> f(h->P.nrep);
     VBC_TRY(h, hipMemcpy(f.data(), h->B.flags, sizeof(uint32_t) * h->P.nrep, hipMemcpyDeviceToHost),
             "flags readback");
-    if (flags_per_replica) std::memcpy(flags_per_replica, f.data(), sizeof(uint32_t) * h->P.nrep);
+    if (flags_per_replica)
+        for (int r = 0; r < h->P.nrep; ++r) flags_per_replica[r] = f[r] & 0xFFu;
     vbc_status st = VBC_OK;
     for (int r = 0; r < h->P.nrep && st == VBC_OK; ++r) {
         if (f[r] & VBC_FLAG_NONFINITE) {
             st = VBC_ERR_NONFINITE;
             h->err = "replica " + std::to_string(r) + ": non-finite coordinates or forces";
+        } else if (f[r] & VBC_FLAG_STAGE_OVERFLOW) {
+            st = VBC_ERR_CAPACITY;
+            h->err = "replica " + std::to_string(r) +
+                     ": brick slot or staging capacity exceeded (raise stage_cap or lower brick)";
+        } else if (f[r] & VBC_FLAG_LOST) {
+            st = VBC_ERR_NONFINITE;
+            h->err = "replica " + std::to_string(r) +
+                     ": a particle moved more than one cell between list builds (unstable dynamics)";
         } else if (f[r] & VBC_FLAG_NLIST_OVERFLOW) {
             st = VBC_ERR_NLIST_OVERFLOW;
             h->err = "replica " + std::to_string(r) + ": neighbour list overflow (raise k_max)";
-        } else if (f[r] & VBC_FLAG_STAGE_OVERFLOW) {
-            st = VBC_ERR_CAPACITY;
-            h->err = "replica " + std::to_string(r) + ": brick staging overflow (raise stage_cap)";
         }
     }
-    uint32_t errs = VBC_FLAG_NONFINITE | VBC_FLAG_NLIST_OVERFLOW | VBC_FLAG_STAGE_OVERFLOW;
+    uint32_t errs = VBC_FLAG_NONFINITE | VBC_FLAG_NLIST_OVERFLOW | VBC_FLAG_STAGE_OVERFLOW | VBC_FLAG_LOST;
     VBC_TRY(h, launch_flags(h->B, h->P, errs, false, s), "flags");
     VBC_TRY(h, hipStreamSynchronize(s), "sync");
     return st;
@@ -577,9 +674,76 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
     if (!h || !d_count || (cap > 0 && !d_pairs)) return fail(VBC_ERR_ARG, "NULL argument");
     if (rep < 0 || rep >= h->P.nrep) { h->err = "replica index out of range"; return VBC_ERR_ARG; }
     if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    VBC_LAYOUT(h, s);
     VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
     VBC_TRY(h, launch_export_nlist(h->B, h->P, rep, h->reps[rep].nbrick, d_pairs, cap, d_count, s),
             "export");
+    return VBC_OK;
+}
+
+vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out)
+{
+    if (!h || !out) return fail(VBC_ERR_ARG, "NULL argument");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
+    std::vector<unsigned long long> v(4 * (size_t)h->P.nrep), ev(h->P.nbrick_tot);
+    std::vector<uint32_t> en(h->P.nbrick_tot);
+    VBC_TRY(h, hipMemcpy(v.data(), h->B.stats, sizeof(unsigned long long) * v.size(),
+                         hipMemcpyDeviceToHost),
+            "stats readback");
+    VBC_TRY(h, hipMemcpy(ev.data(), h->B.bevals, sizeof(unsigned long long) * ev.size(),
+                         hipMemcpyDeviceToHost),
+            "stats readback");
+    VBC_TRY(h, hipMemcpy(en.data(), h->B.bentries, sizeof(uint32_t) * en.size(),
+                         hipMemcpyDeviceToHost),
+            "stats readback");
+    for (int r = 0; r < h->P.nrep; ++r) {
+        const RepDev &R = h->reps[r];
+        unsigned long long pe = 0, le = 0;
+        for (int b = 0; b < R.nbrick; ++b) {
+            pe += ev[R.b_off + b];
+            le += en[R.b_off + b];
+        }
+        out[r].builds = v[4 * r];
+        out[r].list_entries = le;
+        out[r].pair_evals = pe;
+        out[r].evals = v[4 * r + 3];
+    }
+    return VBC_OK;
+}
+
+vbc_status vbc_profile(vbc_handle h, int32_t enable, int32_t max_launches)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    if (enable && max_launches <= 0) { h->err = "max_launches must be > 0"; return VBC_ERR_ARG; }
+    h->prof = enable != 0;
+    for (int k = 0; k < VBC_NK; ++k) h->prof_n[k] = 0;
+    if (!h->prof) return VBC_OK;
+    h->prof_max = max_launches;
+    for (int k = 0; k < VBC_NK; ++k)
+        for (int e = 0; e < 2; ++e)
+            while ((int)h->ev[k][e].size() < max_launches) {
+                hipEvent_t x;
+                VBC_TRY(h, hipEventCreate(&x), "hipEventCreate");
+                h->ev[k][e].push_back(x);
+            }
+    return VBC_OK;
+}
+
+vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms, int64_t *launches)
+{
+    if (!h || !ms || !launches) return fail(VBC_ERR_ARG, "NULL argument");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
+    for (int k = 0; k < VBC_NK; ++k) {
+        double tot = 0.0;
+        for (int i = 0; i < h->prof_n[k]; ++i) {
+            float t = 0.0f;
+            VBC_TRY(h, hipEventElapsedTime(&t, h->ev[k][0][i], h->ev[k][1][i]), "hipEventElapsedTime");
+            tot += t;
+        }
+        ms[k] = tot;
+        launches[k] = h->prof_n[k];
+        h->prof_n[k] = 0;
+    }
     return VBC_OK;
 }
 

@@ -1,11 +1,13 @@
 // vbc_internal.h -- device-side data layout of libvbc (gfx950).
 //
-// Particles of every replica live in one flat index space, sorted per replica by cell
-// rank.  Cells are ranked brick-major: a "brick" is a block of up to bd^3 cells owned by
-// one workgroup, and the cells of one brick have consecutive ranks, so the particles a
-// workgroup owns are one contiguous range.  A workgroup stages its own particles and the
-// one-cell halo around its brick in LDS; the neighbour list stores, per particle, 16-bit
-// indices into that staging order.
+// Space is cut into cells of edge >= the list radius, and cells into "bricks" of up to
+// bd^3 cells; one workgroup owns one brick.  Every brick has a fixed number of particle
+// slots (bcap), so a replica's particles live in nbrick * bcap slots without any global
+// prefix sum: brick b of replica r owns slots [p_off + b * bcap, p_off + b * bcap + bcnt[b]),
+// sorted by cell (cells in x-fastest order inside the brick) and by tag inside a cell.
+// A workgroup stages its own particles and the one-cell halo around its brick in LDS in a
+// brick-local frame; the neighbour list stores per particle 16-bit indices into that
+// staging order, in chunks of eight (one 16-byte load per chunk).
 #pragma once
 #include <stdint.h>
 
@@ -16,6 +18,7 @@ namespace vbc {
 constexpr int MAXT = 4;          // particle types per replica
 constexpr int MAX_BRICK = 6;     // cells per brick edge
 constexpr int NH_MAX = (MAX_BRICK + 2) * (MAX_BRICK + 2) * (MAX_BRICK + 2);
+constexpr int CHUNK = 8;         // list entries per 16-byte chunk
 
 // Derived constants of one type pair.  Everything the kernels need is precomputed on
 // the host in FP64 from vbc_pair_params.
@@ -34,11 +37,11 @@ struct PairDev {
 };
 
 struct RepDev {
-    int64_t p_off;         // first internal (sorted) index of this replica
+    int64_t p_off;         // first slot of this replica
     int64_t n;             // particles
     int64_t o_off;         // first caller-order index
-    int32_t c_off;         // offset into cell_rank (ncell entries per replica)
-    int32_t cs_off;        // offset into cell_start (ncell + 1 entries per replica)
+    int32_t bcap;          // slots per brick
+    int32_t c_off;         // offset into the per-cell tables (ncell entries per replica)
     int32_t b_off;         // first global brick id
     int32_t nbrick;
     int32_t ncell;
@@ -56,54 +59,63 @@ struct RepDev {
     PairDev pair[MAXT * MAXT];
 };
 
-// Pointers into the caller's workspace.
+// Pointers into the caller's workspace.  [2] = {live, next}: a list build writes the new
+// sorted layout into "next" and the list kernel copies each brick into "live".
 struct Buffers {
-    RepDev *reps;           // [nrep]
-    int32_t *cell_rank;     // [sum ncell]  cell linear index -> brick-major rank
-    int32_t *brick_rank0;   // [nbrick_tot] rank of a brick's first cell
-    int32_t *cell_cnt;      // [sum ncell]  binning counters (kept zero between builds)
-    int64_t *cell_start;    // [sum (ncell+1)] internal index of each rank's first particle
-    double *x[2];           // positions, SoA [3][ntot], double-buffered by step parity
-    double *v;              // velocities SoA [3][ntot]
-    double *Fst;            // forces kept between calls SoA [3][ntot]
-    double *xref;           // positions at the last build SoA [3][ntot]
-    int32_t *tag;           // [ntot] tag of each internal slot
-    int32_t *type;          // [ntot]
-    int32_t *pcell;         // [ntot] cell rank of each particle at the last build
-    int64_t *inv;           // [ntot] replica-local tag -> internal index (by p_off + tag)
-    // rebuild scratch
-    int32_t *slot;          // [ntot]
-    int32_t *perm;          // [ntot]
-    double *xs;             // [3][ntot]
-    double *vs;             // [3][ntot]
-    int32_t *tags;          // [ntot]
-    int32_t *types;         // [ntot]
-    int32_t *pcs;           // [ntot]
-    // list
-    uint16_t *nl;           // [k_max][ntot]
-    uint16_t *nn;           // [ntot]
-    // pass outputs
-    double *nd;             // [ntot] counts (FP64)
-    void *sA;               // [ntot] (s or n, A) as float2 / double2
-    uint8_t *win;           // [nbrick_tot] brick holds a particle inside a switching window
-    double *part;           // [nbrick_tot][8] per-brick energy/virial partial sums
-    uint32_t *flags;        // [nrep]
-    uint64_t *step;         // [nrep] step counter (noise counter)
+    RepDev *reps;            // [nrep]
+    int32_t *cell_rank;      // [sum ncell]  cell linear index -> brick-major rank (static)
+    int32_t *brick_rank0;    // [nbrick_tot] rank of a brick's first cell (static)
+    int32_t *cstart[2];      // [sum ncell] first slot of each cell (by rank)
+    int32_t *ccnt[2];        // [sum ncell] particles in each cell (by rank)
+    int32_t *bcnt[2];        // [nbrick_tot] particles in each brick
+    int32_t *bfill;          // [nbrick_tot] counters of the full (unsorted-input) build
+    double *x[2];            // positions SoA [3][nslots], double-buffered by step parity
+    double *v;               // velocities SoA [3][nslots]
+    double *Fst;             // forces kept between calls SoA [3][nslots]
+    double *xref;            // positions at the last build SoA [3][nslots]
+    int32_t *tag;            // [nslots]
+    int32_t *type;           // [nslots]
+    uint8_t *lcell;          // [nslots] cell of the particle inside its brick
+    double *xs;              // next layout: positions SoA [3][nslots]
+    double *vs;              // next layout: velocities
+    int32_t *tags, *types;   // next layout
+    uint8_t *lcells;         // next layout
+    int32_t *src;            // [nslots] full build: members of each brick (dense index)
+    int32_t *inv;            // [ntot] caller index (o_off + tag) -> slot
+    uint4 *nl;               // [nchunk][nslots] neighbour list chunks of 8 x uint16
+    uint16_t *nn;            // [nslots] list length
+    double *nd;              // [nslots] counts (FP64)
+    void *sA;                // [nslots] (s or n, A) as float2 / double2
+    uint8_t *win;            // [nbrick_tot] brick holds a particle inside a switching window
+    double *part;            // [nbrick_tot][8] per-brick energy/virial partial sums
+    uint32_t *flags;         // [nrep]
+    uint64_t *step;          // [nrep] step counter (noise counter)
+    unsigned long long *stats;  // [nrep][4] builds, -, -, count passes
+    unsigned long long *bevals; // [nbrick_tot] pair evaluations of each brick, summed over passes
+    uint32_t *bentries;         // [nbrick_tot] list entries of each brick at the last build
 };
 
 struct Launch {
     int nrep;
-    int64_t ntot;
-    int32_t ncell_tot;      // sum ncell
-    int32_t ncs_tot;        // sum (ncell + 1)
+    int64_t ntot;            // particles
+    int64_t nslots;          // slots (sum nbrick * bcap)
+    int32_t ncell_tot;
     int32_t nbrick_tot;
-    int32_t k_max;
+    int32_t k_max;           // multiple of CHUNK
+    int32_t nchunk;          // k_max / CHUNK
     int32_t block;
     int32_t stage_cap;
-    int32_t nh_max;         // max halo-grid cells of any brick
+    int32_t nh_max;          // max halo-grid cells of any brick
+    int32_t bcap_max;
+    int32_t ncb_max;         // max cells of one brick
     int32_t ntypes_max;
     int32_t any_chains;
     int32_t precision;
+};
+
+// internal flag bits (beyond the public ones in vbc.h)
+enum : uint32_t {
+    FLAG_FULL = 1u << 8      // next build starts from unsorted (caller-order) input
 };
 
 enum Mode { MODE_EVAL = 0, MODE_MID = 1, MODE_LAST = 2 };
@@ -117,12 +129,14 @@ struct StepArgs {
 };
 
 // host-side launchers (vbc_kernels.hip)
-hipError_t launch_set_state(const Buffers &B, const Launch &P, int rep_lo, int rep_hi,
-                            const double *x, const double *v, const int32_t *type,
-                            uint64_t step0, hipStream_t s, int64_t n_in, int64_t in_off);
-hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int rep_lo, int rep_hi,
-                            double *x, double *v, hipStream_t s, int64_t n_out, int64_t out_off);
+hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, const double *x,
+                            const double *v, const int32_t *type, uint64_t step0, hipStream_t s,
+                            int64_t n_in, int64_t in_off);
+hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int64_t slot_lo,
+                            int64_t nslot, int64_t out_off, int64_t out_stride, double *x,
+                            double *v, hipStream_t s);
 hipError_t launch_flags(const Buffers &B, const Launch &P, uint32_t bits, bool set, hipStream_t s);
+hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, hipStream_t s);
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s);
@@ -134,6 +148,7 @@ hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const S
 hipError_t launch_advance(const Buffers &B, const Launch &P, uint64_t nsteps, hipStream_t s);
 hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int nbrick,
                                int32_t *pairs, int64_t cap, int64_t *count, hipStream_t s);
+size_t lds_bytes_sort(const Launch &P);
 size_t lds_bytes_nlist(const Launch &P);
 size_t lds_bytes_count(const Launch &P);
 size_t lds_bytes_embed(const Launch &P);

@@ -12,9 +12,15 @@
 // The energy gradient needs A of every counted neighbour, which is only final once all
 // counts are, hence the separate sparse embed pass between the two list sweeps.
 //
-// Data flow of one workgroup: it owns one cell brick; it stages its own particles and the
-// one-cell halo around the brick into LDS in a brick-local frame, then sweeps each own
-// particle's list (16-bit indices into that staging order) reading neighbours from LDS.
+// List build (when some particle has moved more than half the buffer): every workgroup
+// gathers the particles now inside its brick from the one-cell halo of the previous
+// layout, orders them by (cell, tag) in LDS and writes the next layout; a second kernel
+// copies each brick to the live arrays and builds its list.  Starting from unsorted input
+// (after vbc_set_state), particles are first binned into per-brick buckets with atomics.
+//
+// Data flow of one workgroup in a pass: it owns one brick; it stages its own particles and
+// the halo into LDS in a brick-local frame, then sweeps each own particle's list (16-bit
+// indices into the staging order, eight per 16-byte chunk) reading neighbours from LDS.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,6 +31,7 @@
 namespace vbc {
 
 #define VBC_WAVE 64
+#define VBC_GROUP 8  // lanes that copy one cell during staging
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -40,34 +47,28 @@ template <> struct V2<double> { using t = double2; };
 __device__ __forceinline__ float rsqrt_r(float x) { return __frsqrt_rn(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 
-__device__ __forceinline__ int rep_of_particle(const RepDev *R, int nrep, int64_t i)
+template <class F>
+__device__ __forceinline__ int bsearch_last(int nrep, F key, int64_t v)
 {
     int lo = 0, hi = nrep - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (R[mid].p_off <= i) lo = mid; else hi = mid - 1;
+        if (key(mid) <= v) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
+__device__ __forceinline__ int rep_of_slot(const RepDev *R, int nrep, int64_t i)
+{
+    return bsearch_last(nrep, [&](int k) { return R[k].p_off; }, i);
+}
+__device__ __forceinline__ int rep_of_caller(const RepDev *R, int nrep, int64_t g)
+{
+    return bsearch_last(nrep, [&](int k) { return R[k].o_off; }, g);
+}
 __device__ __forceinline__ int rep_of_brick(const RepDev *R, int nrep, int b)
 {
-    int lo = 0, hi = nrep - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (R[mid].b_off <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int rep_of_cell(const RepDev *R, int nrep, int c)
-{
-    int lo = 0, hi = nrep - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (R[mid].c_off <= c) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    return bsearch_last(nrep, [&](int k) { return (int64_t)R[k].b_off; }, b);
 }
 
 // Map workgroups to bricks so that consecutive bricks (which share halo cells) land on
@@ -106,15 +107,6 @@ __device__ __forceinline__ Real omega_r(Real x, Real x1, Real x2)
     u = u < Real(0) ? Real(0) : (u > Real(1) ? Real(1) : u);
     Real q = Real(1) - u * u;
     return q * q;
-}
-
-template <class Real>
-__device__ __forceinline__ Real omega_dr(Real x, Real x1, Real x2)
-{
-    Real w = x2 - x1;
-    Real u = (x - x1) / w;
-    if (!(u > Real(0) && u < Real(1))) return Real(0);
-    return Real(-4) * u * (Real(1) - u * u) / w;
 }
 
 // Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11): two 64x64->128-bit
@@ -164,214 +156,56 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// ---------------------------------------------------------------------------
-// state in / out
-// ---------------------------------------------------------------------------
-
-__global__ void k_set_state(Buffers B, int nrep, int64_t ntot, int rep_lo, int rep_hi,
-                            int64_t in_off, int64_t in_stride, const double *__restrict__ x,
-                            const double *__restrict__ v, const int32_t *__restrict__ type,
-                            uint64_t step0)
+// Exclusive scan of a[0..n) in place by the first wave; returns the total (valid in the
+// first wave).  Call from all threads of the block between barriers.
+__device__ __forceinline__ int wave0_exclusive_scan(int *a, int n)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t lo = B.reps[rep_lo].p_off;
-    int64_t hi = B.reps[rep_hi].p_off + B.reps[rep_hi].n;
-    int64_t k = lo + i;  // internal index == caller index when freshly set
-    if (k >= hi) return;
-    int r = rep_of_particle(B.reps, nrep, k);
-    const RepDev &R = B.reps[r];
-    int64_t tg = k - R.p_off;
-    int64_t src = R.o_off + tg - in_off;
-    for (int a = 0; a < 3; ++a) {
-        B.x[0][a * ntot + k] = x[a * in_stride + src];
-        B.x[1][a * ntot + k] = x[a * in_stride + src];
-        B.v[a * ntot + k] = v ? v[a * in_stride + src] : 0.0;
-    }
-    B.tag[k] = (int32_t)tg;
-    int ty = type ? type[src] : 0;
-    B.type[k] = (ty >= 0 && ty < R.ntypes) ? ty : 0;
-    B.inv[k] = k;
-    if (tg == 0) {
-        B.step[r] = step0;
-        B.flags[r] = VBC_FLAG_REBUILD;
-    }
-}
-
-__global__ void k_get_state(Buffers B, int nrep, int64_t ntot, int cur, int rep_lo, int rep_hi,
-                            int64_t out_off, int64_t out_stride, double *__restrict__ x,
-                            double *__restrict__ v)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t lo = B.reps[rep_lo].p_off;
-    int64_t hi = B.reps[rep_hi].p_off + B.reps[rep_hi].n;
-    int64_t k = lo + i;
-    if (k >= hi) return;
-    int r = rep_of_particle(B.reps, nrep, k);
-    const RepDev &R = B.reps[r];
-    int64_t dst = R.o_off + B.tag[k] - out_off;
-    for (int a = 0; a < 3; ++a) {
-        if (x) {
-            double t = B.x[cur][a * ntot + k];
-            double L = R.L[a];
-            t = t - L * floor(t / L);
-            if (t >= L) t -= L;
-            if (t < 0.0) t = 0.0;
-            x[a * out_stride + dst] = t;
+    int carry = 0;
+    if (threadIdx.x < VBC_WAVE) {
+        int lane = threadIdx.x;
+        for (int base = 0; base < n; base += VBC_WAVE) {
+            int q = base + lane;
+            int v = q < n ? a[q] : 0;
+            int incl = v;
+#pragma unroll
+            for (int o = 1; o < VBC_WAVE; o <<= 1) {
+                int t = __shfl_up(incl, o, VBC_WAVE);
+                if (lane >= o) incl += t;
+            }
+            if (q < n) a[q] = carry + incl - v;
+            carry += __shfl(incl, VBC_WAVE - 1, VBC_WAVE);
         }
-        if (v) v[a * out_stride + dst] = B.v[a * ntot + k];
     }
+    return carry;
 }
 
-__global__ void k_flags_or(Buffers B, int nrep, uint32_t bits)
+// Wrap one coordinate into [0, L).
+__device__ __forceinline__ double wrap1(double t, double L)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrep) B.flags[r] |= bits;
+    if (t < 0.0 || t >= L) {
+        t = t - L * floor(t / L);
+        if (t >= L) t -= L;
+        if (t < 0.0) t = 0.0;
+    }
+    return t;
 }
 
-__global__ void k_flags_clear(Buffers B, int nrep, uint32_t bits)
+__device__ __forceinline__ int cell_of(double t, double h, int nc)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrep) B.flags[r] &= ~bits;
-}
-
-__global__ void k_advance(Buffers B, int nrep, uint64_t nsteps)
-{
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrep) B.step[r] += nsteps;
+    int c = (int)floor(t / h);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
 // ---------------------------------------------------------------------------
-// neighbour-list build: bin, scan, scatter, sort within cells, list
-// ---------------------------------------------------------------------------
-
-// Wrap into the box, bin by cell (edge h >= list radius), count per cell.
-__global__ void k_bin(Buffers B, int nrep, int64_t ntot, int cur)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntot) return;
-    int r = rep_of_particle(B.reps, nrep, i);
-    const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & VBC_FLAG_REBUILD)) return;
-    int c[3];
-    bool bad = false;
-    for (int a = 0; a < 3; ++a) {
-        double t = B.x[cur][a * ntot + i];
-        if (!isfinite(t)) {
-            bad = true;
-            t = 0.0;
-        }
-        double L = R.L[a];
-        if (t < 0.0 || t >= L) {
-            t = t - L * floor(t / L);
-            if (t >= L) t -= L;
-            if (t < 0.0) t = 0.0;
-        }
-        B.x[cur][a * ntot + i] = t;
-        int ca = (int)floor(t / R.h[a]);
-        c[a] = ca < 0 ? 0 : (ca >= R.nc[a] ? R.nc[a] - 1 : ca);
-    }
-    if (bad) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_NONFINITE);
-    int lin = c[0] + R.nc[0] * (c[1] + R.nc[1] * c[2]);
-    int rank = B.cell_rank[R.c_off + lin];
-    B.pcs[i] = rank;
-    B.slot[i] = atomicAdd(&B.cell_cnt[R.c_off + rank], 1);
-}
-
-// Exclusive scan of the cell counts of one replica (one workgroup per replica); the
-// counters are cleared for the next build.
-__global__ void k_scan(Buffers B, int nrep)
-{
-    int r = blockIdx.x;
-    const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & VBC_FLAG_REBUILD)) return;
-    __shared__ int64_t part[1024];
-    int nt = blockDim.x;
-    int n = R.ncell;
-    int chunk = (n + nt - 1) / nt;
-    int lo = threadIdx.x * chunk;
-    int hi = min(n, lo + chunk);
-    int64_t s = 0;
-    for (int k = lo; k < hi; ++k) s += B.cell_cnt[R.c_off + k];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (int t = 0; t < nt; ++t) {
-            int64_t v = part[t];
-            part[t] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    int64_t acc = R.p_off + part[threadIdx.x];
-    for (int k = lo; k < hi; ++k) {
-        int c = B.cell_cnt[R.c_off + k];
-        B.cell_start[R.cs_off + k] = acc;
-        acc += c;
-        B.cell_cnt[R.c_off + k] = 0;
-    }
-    if (threadIdx.x == 0) B.cell_start[R.cs_off + n] = R.p_off + R.n;
-}
-
-__global__ void k_scatter(Buffers B, int nrep, int64_t ntot)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntot) return;
-    int r = rep_of_particle(B.reps, nrep, i);
-    const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & VBC_FLAG_REBUILD)) return;
-    int64_t dst = B.cell_start[R.cs_off + B.pcs[i]] + B.slot[i];
-    B.perm[dst] = (int32_t)i;
-}
-
-// One thread per cell: order the cell's particles by tag (so the sorted order depends only
-// on positions and tags), then gather every per-particle array into the new order.
-__global__ void k_cellsort(Buffers B, int nrep, int64_t ntot, int ncell_tot, int cur)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell_tot) return;
-    int r = rep_of_cell(B.reps, nrep, c);
-    const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & VBC_FLAG_REBUILD)) return;
-    int rank = c - R.c_off;
-    int64_t s = B.cell_start[R.cs_off + rank];
-    int64_t e = B.cell_start[R.cs_off + rank + 1];
-    for (int64_t p = s + 1; p < e; ++p) {
-        int32_t o = B.perm[p];
-        int32_t key = B.tag[o];
-        int64_t q = p - 1;
-        while (q >= s) {
-            int32_t oq = B.perm[q];
-            if (B.tag[oq] <= key) break;
-            B.perm[q + 1] = oq;
-            --q;
-        }
-        B.perm[q + 1] = o;
-    }
-    for (int64_t p = s; p < e; ++p) {
-        int32_t o = B.perm[p];
-        for (int a = 0; a < 3; ++a) {
-            B.xs[a * ntot + p] = B.x[cur][a * ntot + o];
-            B.vs[a * ntot + p] = B.v[a * ntot + o];
-        }
-        int32_t tg = B.tag[o];
-        B.tags[p] = tg;
-        B.types[p] = B.type[o];
-        B.pcell[p] = rank;
-        B.inv[R.p_off + tg] = p;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// brick staging
+// brick geometry and staging
 // ---------------------------------------------------------------------------
 
 struct StageHdr {
-    int64_t own_start;
+    int64_t base;   // first slot of the brick
     int n_own;
     int total;
     int rank0;
-    int nh;
+    int nh, ncb;
     int c0[3], e[3], H[3];
     double O[3];
     int overflow;
@@ -380,105 +214,12 @@ struct StageHdr {
 struct StageTabs {
     int *q_off;    // staged offset of each halo-grid cell (own and halo)
     int *q_cnt;    // particles in the cell
-    int *q_src;    // first internal index of the cell
+    int *q_src;    // first slot of the cell
     int *q_hpre;   // exclusive prefix of halo-cell counts (own cells contribute 0)
     int *q_w;      // packed image shift (wx+1) | (wy+1) << 2 | (wz+1) << 4
 };
 
 __device__ __forceinline__ int unpack_w(int w, int a) { return ((w >> (2 * a)) & 3) - 1; }
-
-// Lay out the staging of brick lb of replica R: the own cells first (one contiguous run
-// of the sorted order), then every halo cell of the (e+2)^3 grid in x-fastest order.
-// All threads of the block call this.  Uses cell_start of the last build.
-__device__ void stage_tables(const RepDev &R, int lb, const Buffers &B, StageHdr &S,
-                             StageTabs T, int stage_cap)
-{
-    if (threadIdx.x == 0) {
-        int bx = lb % R.nb[0];
-        int by = (lb / R.nb[0]) % R.nb[1];
-        int bz = lb / (R.nb[0] * R.nb[1]);
-        int Bc[3] = {bx, by, bz};
-        int ncb = 1;
-        for (int a = 0; a < 3; ++a) {
-            S.c0[a] = Bc[a] * R.bd[a];
-            S.e[a] = min(R.bd[a], R.nc[a] - S.c0[a]);
-            S.H[a] = S.e[a] + 2;
-            ncb *= S.e[a];
-            S.O[a] = ((double)S.c0[a] + 0.5 * (double)S.e[a]) * R.h[a];
-        }
-        S.nh = S.H[0] * S.H[1] * S.H[2];
-        S.rank0 = B.brick_rank0[R.b_off + lb];
-        S.own_start = B.cell_start[R.cs_off + S.rank0];
-        S.n_own = (int)(B.cell_start[R.cs_off + S.rank0 + ncb] - S.own_start);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < S.nh; q += blockDim.x) {
-        int h[3] = {q % S.H[0], (q / S.H[0]) % S.H[1], q / (S.H[0] * S.H[1])};
-        int g[3], w = 0;
-        bool own = true;
-        for (int a = 0; a < 3; ++a) {
-            int ga = S.c0[a] - 1 + h[a];
-            int wa = ga < 0 ? -1 : (ga >= R.nc[a] ? 1 : 0);
-            g[a] = ga - wa * R.nc[a];
-            w |= (wa + 1) << (2 * a);
-            own = own && (h[a] >= 1 && h[a] <= S.e[a]);
-        }
-        int rank = B.cell_rank[R.c_off + g[0] + R.nc[0] * (g[1] + R.nc[1] * g[2])];
-        int64_t st = B.cell_start[R.cs_off + rank];
-        int cnt = (int)(B.cell_start[R.cs_off + rank + 1] - st);
-        T.q_src[q] = (int)st;
-        T.q_cnt[q] = cnt;
-        T.q_w[q] = w;
-        T.q_off[q] = own ? (int)(st - S.own_start) : -1;
-        T.q_hpre[q] = own ? 0 : cnt;
-    }
-    __syncthreads();
-    // exclusive scan of the halo counts by the first wave
-    if (threadIdx.x < VBC_WAVE) {
-        int lane = threadIdx.x;
-        int carry = 0;
-        for (int base = 0; base < S.nh; base += VBC_WAVE) {
-            int q = base + lane;
-            int v = q < S.nh ? T.q_hpre[q] : 0;
-            int incl = v;
-#pragma unroll
-            for (int o = 1; o < VBC_WAVE; o <<= 1) {
-                int t = __shfl_up(incl, o, VBC_WAVE);
-                if (lane >= o) incl += t;
-            }
-            if (q < S.nh) T.q_hpre[q] = carry + incl - v;
-            carry += __shfl(incl, VBC_WAVE - 1, VBC_WAVE);
-        }
-        if (lane == 0) {
-            S.total = S.n_own + carry;
-            S.overflow = S.total > stage_cap;
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < S.nh; q += blockDim.x)
-        if (T.q_off[q] < 0) T.q_off[q] = S.n_own + T.q_hpre[q];
-    __syncthreads();
-}
-
-// Internal index and image shift of staged slot t.
-__device__ __forceinline__ void stage_source(const StageHdr &S, const StageTabs &T, int t,
-                                             int64_t &src, int &w)
-{
-    if (t < S.n_own) {
-        src = S.own_start + t;
-        w = 0x15;
-        return;
-    }
-    int k = t - S.n_own;
-    int lo = 0, hi = S.nh;  // first q with q_hpre[q] > k
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (T.q_hpre[mid] <= k) lo = mid + 1; else hi = mid;
-    }
-    int q = lo - 1;
-    src = T.q_src[q] + (k - T.q_hpre[q]);
-    w = T.q_w[q];
-}
 
 __device__ __forceinline__ size_t align32(size_t b) { return (b + 31) & ~(size_t)31; }
 
@@ -499,12 +240,257 @@ __device__ __forceinline__ unsigned char *after_tabs(unsigned char *smem, int nh
     return smem + align32((size_t)5 * nh_cap * sizeof(int));
 }
 
-// List build for one brick: copy the brick's particles from the sorted scratch into the
-// live arrays, stage raw FP64 positions of own and halo particles, and list for each own
-// particle every staged j != i with minimum-image r^2 < r_list^2.  The distance is the same
-// expression as the plain definition -- t = x_i - x_j, d = t - L k with k the image of the
-// halo cell, r^2 = (dx dx + dy dy) + dz dz -- without contraction, so the set is exact.
-__global__ void k_nlist(Buffers B, Launch P, int cur)
+// Geometry of brick lb of replica R (one thread).
+__device__ __forceinline__ void brick_geometry(const RepDev &R, int lb, StageHdr &S)
+{
+    int Bc[3] = {lb % R.nb[0], (lb / R.nb[0]) % R.nb[1], lb / (R.nb[0] * R.nb[1])};
+    S.ncb = 1;
+    for (int a = 0; a < 3; ++a) {
+        S.c0[a] = Bc[a] * R.bd[a];
+        S.e[a] = min(R.bd[a], R.nc[a] - S.c0[a]);
+        S.H[a] = S.e[a] + 2;
+        S.ncb *= S.e[a];
+        S.O[a] = ((double)S.c0[a] + 0.5 * (double)S.e[a]) * R.h[a];
+    }
+    S.nh = S.H[0] * S.H[1] * S.H[2];
+    S.base = R.p_off + (int64_t)lb * R.bcap;
+}
+
+// Lay out the staging of brick b (local index lb) of replica R from a set of cell tables:
+// own particles first (the brick's slot range), then every halo cell of the (e+2)^3 grid
+// in x-fastest order.  All threads of the block call this.
+__device__ void stage_tables(const RepDev &R, int b, int lb, const int32_t *brick_rank0,
+                             const int32_t *cell_rank, const int32_t *cstart,
+                             const int32_t *ccnt, const int32_t *bcnt, StageHdr &S,
+                             StageTabs T, int stage_cap)
+{
+    if (threadIdx.x == 0) {
+        brick_geometry(R, lb, S);
+        S.rank0 = brick_rank0[b];
+        S.n_own = bcnt[b];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < S.nh; q += blockDim.x) {
+        int h[3] = {q % S.H[0], (q / S.H[0]) % S.H[1], q / (S.H[0] * S.H[1])};
+        int g[3], w = 0;
+        bool own = true;
+        for (int a = 0; a < 3; ++a) {
+            int ga = S.c0[a] - 1 + h[a];
+            int wa = ga < 0 ? -1 : (ga >= R.nc[a] ? 1 : 0);
+            g[a] = ga - wa * R.nc[a];
+            w |= (wa + 1) << (2 * a);
+            own = own && (h[a] >= 1 && h[a] <= S.e[a]);
+        }
+        int rank = cell_rank[R.c_off + g[0] + R.nc[0] * (g[1] + R.nc[1] * g[2])];
+        int st = cstart[R.c_off + rank];
+        int cnt = ccnt[R.c_off + rank];
+        T.q_src[q] = st;
+        T.q_cnt[q] = cnt;
+        T.q_w[q] = w;
+        T.q_off[q] = own ? (int)(st - S.base) : -1;
+        T.q_hpre[q] = own ? 0 : cnt;
+    }
+    __syncthreads();
+    int tot = wave0_exclusive_scan(T.q_hpre, S.nh);
+    if (threadIdx.x == 0) {
+        S.total = S.n_own + tot;
+        S.overflow = S.total > stage_cap;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < S.nh; q += blockDim.x)
+        if (T.q_off[q] < 0) T.q_off[q] = S.n_own + T.q_hpre[q];
+    __syncthreads();
+}
+
+// Call fn(staged_slot, source_slot, packed_shift) for every staged particle.  Groups of
+// eight lanes take one cell at a time, so no search is needed and the loads of all cells
+// are in flight together.
+template <class F>
+__device__ __forceinline__ void stage_copy(const StageHdr &S, const StageTabs &T, F &&fn)
+{
+    int gid = threadIdx.x / VBC_GROUP, gl = threadIdx.x % VBC_GROUP;
+    int ng = blockDim.x / VBC_GROUP;
+    for (int q = gid; q < S.nh; q += ng) {
+        int off = T.q_off[q], src = T.q_src[q], cnt = T.q_cnt[q], w = T.q_w[q];
+        for (int k = gl; k < cnt; k += VBC_GROUP) fn(off + k, src + k, w);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// state in / out, flags
+// ---------------------------------------------------------------------------
+
+// Caller-order input into the live arrays at slot p_off + tag (the unsorted layout that
+// the next full build starts from).
+__global__ void k_set_state(Buffers B, int nrep, int64_t S_, int cur, int64_t in_off,
+                            int64_t n_in, const double *__restrict__ x,
+                            const double *__restrict__ v, const int32_t *__restrict__ type,
+                            uint64_t step0)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_in) return;
+    int64_t g = in_off + i;
+    int r = rep_of_caller(B.reps, nrep, g);
+    const RepDev &R = B.reps[r];
+    int64_t tg = g - R.o_off;
+    int64_t d = R.p_off + tg;
+    for (int a = 0; a < 3; ++a) {
+        B.x[cur][a * S_ + d] = x[a * n_in + i];
+        B.v[a * S_ + d] = v ? v[a * n_in + i] : 0.0;
+    }
+    B.tag[d] = (int32_t)tg;
+    int ty = type ? type[i] : 0;
+    B.type[d] = (ty >= 0 && ty < R.ntypes) ? ty : 0;
+    if (tg == 0) {
+        B.step[r] = step0;
+        B.flags[r] = VBC_FLAG_REBUILD | FLAG_FULL;
+    }
+}
+
+__global__ void k_get_state(Buffers B, int nrep, int64_t S_, int cur, int64_t slot_lo,
+                            int64_t nslot, int64_t out_off, int64_t out_stride,
+                            double *__restrict__ x, double *__restrict__ v)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nslot) return;
+    int64_t slot = slot_lo + k;
+    int r = rep_of_slot(B.reps, nrep, slot);
+    const RepDev &R = B.reps[r];
+    int64_t loc = slot - R.p_off;
+    int lb = (int)(loc / R.bcap);
+    if (lb >= R.nbrick || loc - (int64_t)lb * R.bcap >= B.bcnt[0][R.b_off + lb]) return;
+    int64_t dst = R.o_off + B.tag[slot] - out_off;
+    for (int a = 0; a < 3; ++a) {
+        if (x) x[a * out_stride + dst] = wrap1(B.x[cur][a * S_ + slot], R.L[a]);
+        if (v) v[a * out_stride + dst] = B.v[a * S_ + slot];
+    }
+}
+
+__global__ void k_flags(Buffers B, int nrep, uint32_t bits, int set)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    if (set) B.flags[r] |= bits; else B.flags[r] &= ~bits;
+}
+
+__global__ void k_advance(Buffers B, int nrep, uint64_t nsteps)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrep) B.step[r] += nsteps;
+}
+
+// ---------------------------------------------------------------------------
+// list build, step 1: the next sorted layout
+// ---------------------------------------------------------------------------
+
+struct SortTabs {
+    int *m_src;    // [bcap] source slot of each member
+    int *m_tag;    // [bcap]
+    int *m_lc;     // [bcap] cell inside the brick
+    int *bucket;   // [bcap] members grouped by cell
+    int *hist;     // [ncb_max]
+    int *cpre;     // [ncb_max]
+    int *fill;     // [ncb_max]
+};
+
+__device__ __forceinline__ SortTabs carve_sort(unsigned char *p, int bcap, int ncb_max)
+{
+    SortTabs T;
+    int *q = (int *)p;
+    T.m_src = q;
+    T.m_tag = q + bcap;
+    T.m_lc = q + 2 * bcap;
+    T.bucket = q + 3 * bcap;
+    T.hist = q + 4 * bcap;
+    T.cpre = T.hist + ncb_max;
+    T.fill = T.cpre + ncb_max;
+    return T;
+}
+
+// Order the nmem members gathered in LDS by (cell, tag), then write them in that order
+// into the next layout of brick b, with the brick's cell tables.  Positions are wrapped
+// into the box as they are copied.  On entry hist holds the members per cell, cpre a
+// copy of it and fill zeros.
+__device__ void place_members(const Buffers &B, const RepDev &R, int r, int b,
+                              const StageHdr &S, SortTabs T, int nmem, int cur, int64_t S_)
+{
+    wave0_exclusive_scan(T.cpre, S.ncb);
+    __syncthreads();
+    for (int m = threadIdx.x; m < nmem; m += blockDim.x) {
+        int lc = T.m_lc[m];
+        int p = T.cpre[lc] + atomicAdd(&T.fill[lc], 1);
+        T.bucket[p] = m;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < nmem; p += blockDim.x) {
+        int m = T.bucket[p];
+        int lc = T.m_lc[m];
+        int lo = T.cpre[lc], hi = lo + T.hist[lc];
+        int key = T.m_tag[m];
+        int rank = 0;
+        for (int k = lo; k < hi; ++k) rank += (T.m_tag[T.bucket[k]] < key) ? 1 : 0;
+        int64_t ns = S.base + lo + rank;
+        int64_t o = T.m_src[m];
+        for (int a = 0; a < 3; ++a) {
+            B.xs[a * S_ + ns] = wrap1(B.x[cur][a * S_ + o], R.L[a]);
+            B.vs[a * S_ + ns] = B.v[a * S_ + o];
+        }
+        B.tags[ns] = key;
+        B.types[ns] = B.type[o];
+        B.lcells[ns] = (uint8_t)lc;
+        B.inv[R.o_off + key] = (int32_t)ns;
+    }
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
+        B.cstart[1][R.c_off + S.rank0 + lc] = (int32_t)(S.base + T.cpre[lc]);
+        B.ccnt[1][R.c_off + S.rank0 + lc] = T.hist[lc];
+    }
+    if (threadIdx.x == 0) B.bcnt[1][b] = nmem;
+}
+
+// Local cell of position x inside brick S, or -1 if the particle is not in the brick.
+__device__ __forceinline__ int local_cell(const RepDev &R, const StageHdr &S, const double *xw)
+{
+    int l[3];
+    for (int a = 0; a < 3; ++a) {
+        int c = cell_of(xw[a], R.h[a], R.nc[a]) - S.c0[a];
+        if (c < 0 || c >= S.e[a]) return -1;
+        l[a] = c;
+    }
+    return l[0] + S.e[0] * (l[1] + S.e[1] * l[2]);
+}
+
+// Full build, part 1: bin unsorted particles into per-brick buckets.
+__global__ void k_gbin(Buffers B, int nrep, int64_t S_, int64_t ntot, int cur)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    int r = rep_of_caller(B.reps, nrep, g);
+    const RepDev &R = B.reps[r];
+    if (!(B.flags[r] & FLAG_FULL)) return;
+    int64_t d = R.p_off + (g - R.o_off);
+    int c[3];
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        double t = B.x[cur][a * S_ + d];
+        if (!isfinite(t)) {
+            bad = true;
+            t = 0.0;
+        }
+        t = wrap1(t, R.L[a]);
+        B.x[cur][a * S_ + d] = t;
+        c[a] = cell_of(t, R.h[a], R.nc[a]) / R.bd[a];
+    }
+    if (bad) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_NONFINITE);
+    int lb = c[0] + R.nb[0] * (c[1] + R.nb[1] * c[2]);
+    int idx = atomicAdd(&B.bfill[R.b_off + lb], 1);
+    if (idx < R.bcap)
+        B.src[R.p_off + (int64_t)lb * R.bcap + idx] = (int32_t)d;
+    else
+        atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
+}
+
+// Full build, part 2: order each bucket and write the next layout.
+__global__ void k_gsort(Buffers B, Launch P, int cur)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
@@ -512,83 +498,273 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
     if (b >= P.nbrick_tot) return;
     int r = rep_of_brick(B.reps, P.nrep, b);
     const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & VBC_FLAG_REBUILD)) return;
+    if (!(B.flags[r] & FLAG_FULL)) return;
+    int lb = b - R.b_off;
+    SortTabs T = carve_sort(smem, P.bcap_max, P.ncb_max);
+    if (threadIdx.x == 0) {
+        brick_geometry(R, lb, S);
+        S.rank0 = B.brick_rank0[b];
+    }
+    __syncthreads();
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
+        T.hist[lc] = 0;
+        T.fill[lc] = 0;
+    }
+    __syncthreads();
+    int nmem = min(B.bfill[b], R.bcap);
+    const int64_t S_ = P.nslots;
+    for (int m = threadIdx.x; m < nmem; m += blockDim.x) {
+        int d = B.src[S.base + m];
+        double xw[3] = {B.x[cur][d], B.x[cur][S_ + d], B.x[cur][2 * S_ + d]};
+        int lc = local_cell(R, S, xw);
+        if (lc < 0) lc = 0;  // not reached: binned from the same wrapped coordinates
+        T.m_src[m] = d;
+        T.m_tag[m] = B.tag[d];
+        T.m_lc[m] = lc;
+        atomicAdd(&T.hist[lc], 1);
+    }
+    __syncthreads();
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) T.cpre[lc] = T.hist[lc];
+    __syncthreads();
+    place_members(B, R, r, b, S, T, nmem, cur, S_);
+    __syncthreads();
+    if (threadIdx.x == 0) B.bfill[b] = 0;
+}
+
+// Incremental build: gather the particles now inside the brick from the one-cell halo of
+// the current layout (a particle moves less than one cell between builds), order them and
+// write the next layout.
+__global__ void k_resort(Buffers B, Launch P, int cur)
+{
+    extern __shared__ __align__(32) unsigned char smem[];
+    __shared__ StageHdr S;
+    __shared__ int nmem_s;
+    int b = brick_of_block();
+    if (b >= P.nbrick_tot) return;
+    int r = rep_of_brick(B.reps, P.nrep, b);
+    const RepDev &R = B.reps[r];
+    uint32_t fl = B.flags[r];
+    if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
+    int lb = b - R.b_off;
+    int nh_cap = (P.nh_max + 3) & ~3;
+    StageTabs Q = carve_tabs(smem, nh_cap);
+    SortTabs T = carve_sort(after_tabs(smem, nh_cap), P.bcap_max, P.ncb_max);
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, Q,
+                 1 << 30);
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
+        T.hist[lc] = 0;
+        T.fill[lc] = 0;
+    }
+    if (threadIdx.x == 0) nmem_s = 0;
+    __syncthreads();
+    const int64_t S_ = P.nslots;
+    const int bcap = R.bcap;
+    stage_copy(S, Q, [&](int t, int src, int w) {
+        double xw[3];
+        for (int a = 0; a < 3; ++a) xw[a] = wrap1(B.x[cur][a * S_ + src], R.L[a]);
+        int lc = local_cell(R, S, xw);
+        if (lc >= 0) {
+            int m = atomicAdd(&nmem_s, 1);
+            if (m < bcap) {
+                T.m_src[m] = src;
+                T.m_tag[m] = B.tag[src];
+                T.m_lc[m] = lc;
+                atomicAdd(&T.hist[lc], 1);
+            }
+        }
+    });
+    __syncthreads();
+    int nmem = nmem_s;
+    if (nmem > bcap) {
+        if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
+        nmem = bcap;
+    }
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) T.cpre[lc] = T.hist[lc];
+    __syncthreads();
+    place_members(B, R, r, b, S, T, nmem, cur, S_);
+}
+
+// ---------------------------------------------------------------------------
+// list build, step 2: copy to live, build the list
+// ---------------------------------------------------------------------------
+
+// Copy brick b of the next layout into the live arrays and list, for each own particle,
+// every staged j != i with minimum-image r^2 < r_list^2.  The decision is exact: the
+// staged FP32 brick-local positions decide every pair whose r^2 is further than 1e-4 from
+// r_list^2 (their error is below 2e-5), and the remaining pairs are tested with the same
+// FP64 expression as the plain definition -- t = x_i - x_j, d = t - L k with k the image
+// of the halo cell, r^2 = (dx dx + dy dy) + dz dz, no contraction.  Entries are written
+// eight at a time as 16-byte chunks.
+__global__ void k_nlist(Buffers B, Launch P, int cur)
+{
+    extern __shared__ __align__(32) unsigned char smem[];
+    __shared__ StageHdr S;
+    __shared__ unsigned long long lost_sum, ent_sum;
+    int b = brick_of_block();
+    if (b >= P.nbrick_tot) return;
+    int r = rep_of_brick(B.reps, P.nrep, b);
+    const RepDev &R = B.reps[r];
+    if (!(B.flags[r] & (VBC_FLAG_REBUILD | FLAG_FULL))) return;
     int lb = b - R.b_off;
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs T = carve_tabs(smem, nh_cap);
-    double *sx = (double *)after_tabs(smem, nh_cap);
-    double *sy = sx + P.stage_cap;
-    double *sz = sy + P.stage_cap;
-    const int64_t ntot = P.ntot;
+    float4 *spos = (float4 *)after_tabs(smem, nh_cap);
+    int *ssrc = (int *)(spos + P.stage_cap);
+    const int64_t S_ = P.nslots;
 
-    stage_tables(R, lb, B, S, T, P.stage_cap);
+    if (threadIdx.x == 0) {
+        lost_sum = 0ull;
+        ent_sum = 0ull;
+    }
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[1], B.ccnt[1], B.bcnt[1], S, T,
+                 P.stage_cap);
 
-    // sorted scratch -> live arrays for the own range
+    // next layout -> live for the own range and the own cell tables
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
+        int64_t i = S.base + t;
         for (int a = 0; a < 3; ++a) {
-            double xa = B.xs[a * ntot + i];
-            B.x[cur][a * ntot + i] = xa;
-            B.xref[a * ntot + i] = xa;
-            B.v[a * ntot + i] = B.vs[a * ntot + i];
+            double xa = B.xs[a * S_ + i];
+            B.x[cur][a * S_ + i] = xa;
+            B.xref[a * S_ + i] = xa;
+            B.v[a * S_ + i] = B.vs[a * S_ + i];
         }
         B.tag[i] = B.tags[i];
         B.type[i] = B.types[i];
+        B.lcell[i] = B.lcells[i];
+    }
+    for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
+        B.cstart[0][R.c_off + S.rank0 + lc] = B.cstart[1][R.c_off + S.rank0 + lc];
+        B.ccnt[0][R.c_off + S.rank0 + lc] = B.ccnt[1][R.c_off + S.rank0 + lc];
+    }
+    if (threadIdx.x == 0) B.bcnt[0][b] = S.n_own;
+    if (lb == 0) {
+        // every particle must have been placed in exactly one brick of the next layout
+        unsigned long long placed = 0;
+        for (int k = threadIdx.x; k < R.nbrick; k += blockDim.x) placed += B.bcnt[1][R.b_off + k];
+        placed = wave_sum(placed);
+        if ((threadIdx.x % VBC_WAVE) == 0 && placed) atomicAdd(&lost_sum, placed);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            B.stats[4 * r + 0] += 1ull;
+            if (lost_sum != (unsigned long long)R.n) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_LOST);
+        }
     }
     if (S.overflow) {
-        for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) B.nn[S.own_start + t] = 0;
-        if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
+        for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) B.nn[S.base + t] = 0;
+        if (threadIdx.x == 0) {
+            atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
+            B.bentries[b] = 0u;
+        }
         return;
     }
-    for (int t = threadIdx.x; t < S.total; t += blockDim.x) {
-        int64_t src;
-        int w;
-        stage_source(S, T, t, src, w);
-        sx[t] = B.xs[src];
-        sy[t] = B.xs[ntot + src];
-        sz[t] = B.xs[2 * ntot + src];
-    }
+    stage_copy(S, T, [&](int t, int src, int w) {
+        float4 p;
+        p.x = (float)((B.xs[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
+        p.y = (float)((B.xs[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
+        p.z = (float)((B.xs[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
+        p.w = 0.0f;
+        spos[t] = p;
+        ssrc[t] = src;
+    });
     __syncthreads();
 
     const double rl2 = R.rlist2;
+    const float lo2 = (float)(rl2 * (1.0 - 2e-5) - 1e-4), hi2 = (float)(rl2 * (1.0 + 2e-5) + 1e-4);
+    const int kmax = P.k_max;
     bool ovf = false;
+    unsigned long long entries = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
-        int loc = B.pcell[i] - S.rank0;
+        int64_t i = S.base + t;
+        int loc = B.lcells[i];
         int lx = loc % S.e[0], ly = (loc / S.e[0]) % S.e[1], lz = loc / (S.e[0] * S.e[1]);
-        double xi = sx[t], yi = sy[t], zi = sz[t];
+        float4 pi = spos[t];
         int nn = 0;
+        uint32_t buf[4] = {0u, 0u, 0u, 0u};
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy)
                 for (int dx = 0; dx < 3; ++dx) {
                     int q = (lx + dx) + S.H[0] * ((ly + dy) + S.H[1] * (lz + dz));
                     int off = T.q_off[q], cnt = T.q_cnt[q], w = T.q_w[q];
-                    double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
-                           kz = (double)unpack_w(w, 2);
                     for (int u = off; u < off + cnt; ++u) {
-                        if (u == t) continue;
-                        double r2;
-                        {
+                        float4 pu = spos[u];
+                        float ex = pi.x - pu.x, ey = pi.y - pu.y, ez = pi.z - pu.z;
+                        float r2f = ex * ex + ey * ey + ez * ez;
+                        if (u == t || !(r2f < hi2)) continue;
+                        bool in = r2f < lo2;
+                        if (!in) {
+                            // near the list radius: decide with the exact FP64 expression
+                            int64_t js = ssrc[u];
+                            double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
+                                   kz = (double)unpack_w(w, 2);
+                            double r2;
+                            {
 #pragma clang fp contract(off)
-                            double tx = xi - sx[u], ty = yi - sy[u], tz = zi - sz[u];
-                            double ddx = tx - R.L[0] * kx;
-                            double ddy = ty - R.L[1] * ky;
-                            double ddz = tz - R.L[2] * kz;
-                            r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                                double tx = B.xs[i] - B.xs[js];
+                                double ty = B.xs[S_ + i] - B.xs[S_ + js];
+                                double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
+                                double ddx = tx - R.L[0] * kx;
+                                double ddy = ty - R.L[1] * ky;
+                                double ddz = tz - R.L[2] * kz;
+                                r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                            }
+                            in = r2 < rl2;
                         }
-                        if (r2 < rl2) {
-                            if (nn < P.k_max) B.nl[(size_t)nn * ntot + i] = (uint16_t)u;
+                        if (in) {
+                            int e = nn & (CHUNK - 1);
+                            uint32_t hv = (uint32_t)u << (16 * (e & 1));
+                            if (e < 2) buf[0] |= hv;
+                            else if (e < 4) buf[1] |= hv;
+                            else if (e < 6) buf[2] |= hv;
+                            else buf[3] |= hv;
                             ++nn;
+                            if ((nn & (CHUNK - 1)) == 0) {
+                                if (nn <= kmax)
+                                    B.nl[(size_t)(nn / CHUNK - 1) * S_ + i] =
+                                        make_uint4(buf[0], buf[1], buf[2], buf[3]);
+                                buf[0] = buf[1] = buf[2] = buf[3] = 0u;
+                            }
                         }
                     }
                 }
-        if (nn > P.k_max) {
+        if ((nn & (CHUNK - 1)) && nn <= kmax)
+            B.nl[(size_t)(nn / CHUNK) * S_ + i] = make_uint4(buf[0], buf[1], buf[2], buf[3]);
+        if (nn > kmax) {
             ovf = true;
-            nn = P.k_max;
+            nn = kmax;
         }
         B.nn[i] = (uint16_t)nn;
+        entries += (unsigned long long)nn;
     }
     if (ovf) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_NLIST_OVERFLOW);
+    entries = wave_sum(entries);
+    if ((threadIdx.x % VBC_WAVE) == 0 && entries) atomicAdd(&ent_sum, entries);
+    __syncthreads();
+    if (threadIdx.x == 0) B.bentries[b] = (uint32_t)ent_sum;
+}
+
+// ---------------------------------------------------------------------------
+// list sweep helper
+// ---------------------------------------------------------------------------
+
+// Visit the list of one own particle: fn(staged index) for each entry, eight entries per
+// 16-byte chunk, with the next chunk's load issued before the current one is processed.
+template <class F>
+__device__ __forceinline__ void for_each_neighbour(const uint4 *__restrict__ nl, int64_t S_,
+                                                   int64_t i, int nn, F &&fn)
+{
+    int nch = (nn + CHUNK - 1) / CHUNK;
+    if (nch == 0) return;
+    const uint4 *lp = nl + i;
+    uint4 q = lp[0];
+    for (int c = 0; c < nch; ++c) {
+        uint4 qn = (c + 1 < nch) ? lp[(size_t)(c + 1) * S_] : q;
+        int m = nn - c * CHUNK;
+        uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int e = 0; e < CHUNK; ++e)
+            if (e < m) fn((int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu));
+        q = qn;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -626,23 +802,28 @@ __device__ __forceinline__ PairR<Real> pair_r(const PairDev &p, double rc2)
     return q;
 }
 
+// Brick-local position of a staged particle: (x + k L) - O, rounded once to Real.
 template <class Real>
-__device__ __forceinline__ void stage_positions(const RepDev &R, const StageHdr &S,
-                                                const StageTabs &T, const double *__restrict__ X,
-                                                int64_t ntot, int t, int64_t &src,
-                                                typename V4<Real>::t *spos, const int32_t *type)
+__device__ __forceinline__ typename V4<Real>::t local_pos(const RepDev &R, const StageHdr &S,
+                                                          const double *__restrict__ X,
+                                                          int64_t S_, int src, int w, int type)
 {
-    int w;
-    stage_source(S, T, t, src, w);
     typename V4<Real>::t p;
-    double lx = (X[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0];
-    double ly = (X[ntot + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1];
-    double lz = (X[2 * ntot + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2];
-    p.x = (Real)lx;
-    p.y = (Real)ly;
-    p.z = (Real)lz;
-    p.w = (Real)type[src];
-    spos[t] = p;
+    p.x = (Real)((X[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
+    p.y = (Real)((X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
+    p.z = (Real)((X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
+    p.w = (Real)type;
+    return p;
+}
+
+template <class Real>
+__device__ __forceinline__ void load_pairs(const RepDev &R, PairR<Real> *pt)
+{
+    const int nt = R.ntypes;
+    if ((int)threadIdx.x < nt * nt) {
+        int a = threadIdx.x / nt, c = threadIdx.x % nt;
+        pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
+    }
 }
 
 template <class Real, bool MULTI>
@@ -653,6 +834,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ int any_win;
+    __shared__ unsigned long long ev_sum;
     __shared__ PairR<Real> pt[MAXT * MAXT];
     int b = brick_of_block();
     if (b >= P.nbrick_tot) return;
@@ -663,18 +845,18 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs T = carve_tabs(smem, nh_cap);
     R4 *spos = (R4 *)after_tabs(smem, nh_cap);
-    const int64_t ntot = P.ntot;
-    const int nt = R.ntypes;
-    if (threadIdx.x < nt * nt) {
-        int a = threadIdx.x / nt, c = threadIdx.x % nt;
-        pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
+    const int64_t S_ = P.nslots;
+    load_pairs<Real>(R, pt);
+    if (threadIdx.x == 0) {
+        any_win = 0;
+        ev_sum = 0ull;
     }
-    if (threadIdx.x == 0) any_win = 0;
-    stage_tables(R, lb, B, S, T, P.stage_cap);
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
+                 P.stage_cap);
     R2 *sA = (R2 *)B.sA;
     if (S.overflow) {
         for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-            int64_t i = S.own_start + t;
+            int64_t i = S.base + t;
             B.nd[i] = 0.0;
             sA[i] = R2{Real(0), Real(0)};
         }
@@ -684,36 +866,34 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         }
         return;
     }
-    for (int t = threadIdx.x; t < S.total; t += blockDim.x) {
-        int64_t src;
-        stage_positions<Real>(R, S, T, B.x[cur], ntot, t, src, spos, B.type);
-    }
+    const double *X = B.x[cur];
+    stage_copy(S, T, [&](int t, int src, int w) {
+        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
+    });
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
     bool win = false;
+    unsigned long long evals = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
+        int64_t i = S.base + t;
         R4 pi = spos[t];
         int ti = MULTI ? (int)pi.w : 0;
-        int nn = B.nn[i];
-        const uint16_t *lp = B.nl + i;
-        int whole = 0;
+        int whole = 0, inside = 0;
         double frac = 0.0;
-        for (int s = 0; s < nn; ++s) {
-            int u = lp[(size_t)s * ntot];
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
+            inside += (r2 < p0.rc2) ? 1 : 0;
             if (MULTI) {
                 int tj = (int)pj.w;
-                if (!((R.mask[ti] >> tj) & 1u)) continue;
+                if (!((R.mask[ti] >> tj) & 1u)) return;
                 const PairR<Real> &q = pt[ti * MAXT + tj];
                 if (r2 <= q.rl2) {
                     ++whole;
                 } else if (r2 < q.rh2) {
-                    Real rr = sqrt(r2);
-                    Real uu = (rr - q.r_l) * q.inv_dw;
+                    Real uu = (sqrt(r2) - q.r_l) * q.inv_dw;
                     Real qq = Real(1) - uu * uu;
                     frac += (double)(qq * qq);
                 }
@@ -721,33 +901,38 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
                 if (r2 <= p0.rl2) {
                     ++whole;
                 } else if (r2 < p0.rh2) {
-                    Real rr = sqrt(r2);
-                    Real uu = (rr - p0.r_l) * p0.inv_dw;
+                    Real uu = (sqrt(r2) - p0.r_l) * p0.inv_dw;
                     Real qq = Real(1) - uu * uu;
                     frac += (double)(qq * qq);
                 }
             }
-        }
+        });
         double n = (double)whole + frac;
+        evals += (unsigned long long)inside;
         B.nd[i] = n;
         if (MULTI) {
             // the switching factor depends on the pair: keep the count itself
             sA[i] = R2{(Real)n, Real(0)};
-            for (int u = 0; u < nt; ++u) {
+            for (int u = 0; u < R.ntypes; ++u) {
                 const PairDev &pd = R.pair[ti * MAXT + u];
                 if (pd.attract && n > pd.x1 && n < pd.x2) win = true;
             }
         } else {
             const PairDev &pd = R.pair[0];
-            double s = omega_d64(n, pd.x1, pd.x2);
-            sA[i] = R2{(Real)s, Real(0)};
+            sA[i] = R2{(Real)omega_d64(n, pd.x1, pd.x2), Real(0)};
             if (pd.attract && n > pd.x1 && n < pd.x2) win = true;
         }
         if (n_out) n_out[R.o_off + B.tag[i]] = n;
     }
     if (win) any_win = 1;
+    evals = wave_sum(evals);
+    if ((threadIdx.x % VBC_WAVE) == 0 && evals) atomicAdd(&ev_sum, evals);
     __syncthreads();
-    if (threadIdx.x == 0) B.win[b] = (uint8_t)any_win;
+    if (threadIdx.x == 0) {
+        B.win[b] = (uint8_t)any_win;
+        B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
+        if (lb == 0) B.stats[4 * r + 3] += 1ull;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -772,31 +957,28 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     StageTabs T = carve_tabs(smem, nh_cap);
     R4 *spos = (R4 *)after_tabs(smem, nh_cap);
     Real *ss = (Real *)(spos + P.stage_cap);
-    const int64_t ntot = P.ntot;
-    const int nt = R.ntypes;
-    if (threadIdx.x < nt * nt) {
-        int a = threadIdx.x / nt, c = threadIdx.x % nt;
-        pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
-    }
-    stage_tables(R, lb, B, S, T, P.stage_cap);
+    const int64_t S_ = P.nslots;
+    load_pairs<Real>(R, pt);
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
+                 P.stage_cap);
     if (S.overflow) return;
     R2 *sA = (R2 *)B.sA;
-    for (int t = threadIdx.x; t < S.total; t += blockDim.x) {
-        int64_t src;
-        stage_positions<Real>(R, S, T, B.x[cur], ntot, t, src, spos, B.type);
+    const double *X = B.x[cur];
+    stage_copy(S, T, [&](int t, int src, int w) {
+        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
         ss[t] = sA[src].x;
-    }
+    });
     __syncthreads();
     const PairR<Real> p0 = pt[0];
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
+        int64_t i = S.base + t;
         double n_i = B.nd[i];
         R4 pi = spos[t];
         int ti = MULTI ? (int)pi.w : 0;
         double sd_i = 0.0;
         bool any = false;
         if (MULTI) {
-            for (int u = 0; u < nt; ++u) {
+            for (int u = 0; u < R.ntypes; ++u) {
                 const PairDev &pd = R.pair[ti * MAXT + u];
                 if (pd.attract && n_i > pd.x1 && n_i < pd.x2) any = true;
             }
@@ -805,38 +987,31 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
             any = R.pair[0].attract && sd_i != 0.0;
         }
         if (!any) continue;
-        int nn = B.nn[i];
-        const uint16_t *lp = B.nl + i;
         double acc = 0.0;
-        for (int s = 0; s < nn; ++s) {
-            int u = lp[(size_t)s * ntot];
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
             if (MULTI) {
                 int tj = (int)pj.w;
                 const PairR<Real> &q = pt[ti * MAXT + tj];
-                if (!q.attract) continue;
-                Real rr = sqrt(r2);
-                Real uu = (rr - q.m) * q.inv_w;
+                if (!q.attract) return;
+                Real uu = (sqrt(r2) - q.m) * q.inv_w;
                 Real qq = Real(1) - uu * uu;
-                if (!(qq > Real(0))) continue;
-                Real va = -q.E_a * qq * qq;
+                if (!(qq > Real(0))) return;
                 const PairDev &pd = R.pair[ti * MAXT + tj];
                 double sdi = omega_dd64(n_i, pd.x1, pd.x2);
-                if (sdi == 0.0) continue;
+                if (sdi == 0.0) return;
                 Real sj = omega_r<Real>(ss[u], q.x1, q.x2);
-                acc += sdi * (double)(sj * va);
+                acc += sdi * (double)(sj * (-q.E_a * qq * qq));
             } else {
-                Real rr = sqrt(r2);
-                Real uu = (rr - p0.m) * p0.inv_w;
+                Real uu = (sqrt(r2) - p0.m) * p0.inv_w;
                 Real qq = Real(1) - uu * uu;
-                if (!(qq > Real(0))) continue;
+                if (!(qq > Real(0))) return;
                 acc += (double)(ss[u] * (-p0.E_a * qq * qq));
             }
-        }
-        double A = MULTI ? acc : sd_i * acc;
-        sA[i].y = (Real)A;
+        });
+        sA[i].y = (Real)(MULTI ? acc : sd_i * acc);
     }
 }
 
@@ -887,25 +1062,23 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     StageTabs T = carve_tabs(smem, nh_cap);
     R4 *spos = (R4 *)after_tabs(smem, nh_cap);
     R2 *ssa = (R2 *)(spos + P.stage_cap);
+    const int64_t S_ = P.nslots;
     const int64_t ntot = P.ntot;
-    const int nt = R.ntypes;
-    if (threadIdx.x < nt * nt) {
-        int a = threadIdx.x / nt, c = threadIdx.x % nt;
-        pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
-    }
+    load_pairs<Real>(R, pt);
     if (threadIdx.x == 0) moved = 0;
-    stage_tables(R, lb, B, S, T, P.stage_cap);
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
+                 P.stage_cap);
     const R2 *sA = (const R2 *)B.sA;
     if (S.overflow) {
         if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
         if (THERMO && threadIdx.x < 8) B.part[(size_t)b * 8 + threadIdx.x] = 0.0;
         return;
     }
-    for (int t = threadIdx.x; t < S.total; t += blockDim.x) {
-        int64_t src;
-        stage_positions<Real>(R, S, T, B.x[cur], ntot, t, src, spos, B.type);
+    const double *X = B.x[cur];
+    stage_copy(S, T, [&](int t, int src, int w) {
+        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
         ssa[t] = sA[src];
-    }
+    });
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
@@ -913,16 +1086,13 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
     bool bad = false, mv = false;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
+        int64_t i = S.base + t;
         R4 pi = spos[t];
         R2 sai = ssa[t];
         int ti = MULTI ? (int)pi.w : 0;
-        int nn = B.nn[i];
-        const uint16_t *lp = B.nl + i;
         Real fx = 0, fy = 0, fz = 0, ei = 0;
         Real w0 = 0, wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
-        for (int s = 0; s < nn; ++s) {
-            int u = lp[(size_t)s * ntot];
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
@@ -930,7 +1100,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
             if (MULTI) {
                 int tj = (int)pj.w;
                 const PairR<Real> &q = pt[ti * MAXT + tj];
-                if (!(r2 < q.rc2)) continue;
+                if (!(r2 < q.rc2)) return;
                 R2 saj = ssa[u];
                 Real rinv = rsqrt_r(r2 > Real(1e-30) ? r2 : Real(1e-30));
                 Real rr = r2 * rinv;
@@ -953,7 +1123,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 uc = uc < Real(0) ? Real(0) : (uc > Real(1) ? Real(1) : uc);
                 phr += asum * q.c_c * uc * (Real(1) - uc * uc) * rinv;
             } else {
-                if (!(r2 < p0.rc2)) continue;
+                if (!(r2 < p0.rc2)) return;
                 R2 saj = ssa[u];
                 Real rinv = rsqrt_r(r2 > Real(1e-30) ? r2 : Real(1e-30));
                 Real rr = r2 * rinv;
@@ -984,21 +1154,20 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 wxz -= phr * dx * dz;
                 wyz -= phr * dy * dz;
             }
-        }
+        });
         double F[3] = {(double)fx, (double)fy, (double)fz};
         double eb = 0.0, wb[7] = {0, 0, 0, 0, 0, 0, 0};
-        const double *X = B.x[cur];
-        double xi_[3] = {X[i], X[ntot + i], X[2 * ntot + i]};
+        double xi_[3] = {X[i], X[S_ + i], X[2 * S_ + i]};
         int32_t tg = B.tag[i];
         if (R.chain_len > 1) {
             // harmonic bonds to the neighbouring beads of the same chain
             int bead = tg % R.chain_len;
             for (int side = -1; side <= 1; side += 2) {
                 if ((side < 0 && bead == 0) || (side > 0 && bead == R.chain_len - 1)) continue;
-                int64_t j = B.inv[R.p_off + tg + side];
+                int64_t j = B.inv[R.o_off + tg + side];
                 double d[3];
                 for (int a = 0; a < 3; ++a) {
-                    double tt = xi_[a] - X[a * ntot + j];
+                    double tt = xi_[a] - X[a * S_ + j];
                     d[a] = tt - R.L[a] * rint(tt / R.L[a]);
                 }
                 double rb = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
@@ -1031,22 +1200,22 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
             if (e_out) e_out[R.o_off + tg] = e_i;
         }
         if (mode == MODE_EVAL) {
-            for (int a = 0; a < 3; ++a) B.Fst[a * ntot + i] = F[a];
+            for (int a = 0; a < 3; ++a) B.Fst[a * S_ + i] = F[a];
             if (F_out)
                 for (int a = 0; a < 3; ++a) F_out[a * ntot + R.o_off + tg] = F[a];
         } else {
-            double vv[3] = {B.v[i], B.v[ntot + i], B.v[2 * ntot + i]};
+            double vv[3] = {B.v[i], B.v[S_ + i], B.v[2 * S_ + i]};
             double xx[3] = {xi_[0], xi_[1], xi_[2]};
             integrate_one(st, mode, false, F, vv, xx, st.seed, (uint64_t)tg, step);
-            for (int a = 0; a < 3; ++a) B.v[a * ntot + i] = vv[a];
+            for (int a = 0; a < 3; ++a) B.v[a * S_ + i] = vv[a];
             if (mode == MODE_LAST) {
-                for (int a = 0; a < 3; ++a) B.Fst[a * ntot + i] = F[a];
+                for (int a = 0; a < 3; ++a) B.Fst[a * S_ + i] = F[a];
             } else {
                 double *Xn = B.x[cur ^ 1];
                 double d2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    Xn[a * ntot + i] = xx[a];
-                    double dd = xx[a] - B.xref[a * ntot + i];
+                    Xn[a * S_ + i] = xx[a];
+                    double dd = xx[a] - B.xref[a * S_ + i];
                     d2 += dd * dd;
                 }
                 if (d2 > R.disp2) mv = true;
@@ -1063,9 +1232,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (moved) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
-    }
+    if (threadIdx.x == 0 && moved) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
     if (THERMO && threadIdx.x < 8) {
         int nw = blockDim.x / VBC_WAVE;
         double s = 0.0;
@@ -1075,25 +1242,28 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
 }
 
 // Opening half-kick and drift of the first step of a call, from the forces kept in Fst.
-__global__ void k_kick_drift(Buffers B, int nrep, int64_t ntot, int cur, StepArgs st)
+__global__ void k_kick_drift(Buffers B, int nrep, int64_t S_, int cur, StepArgs st)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ntot) return;
-    int r = rep_of_particle(B.reps, nrep, i);
+    if (i >= S_) return;
+    int r = rep_of_slot(B.reps, nrep, i);
     const RepDev &R = B.reps[r];
+    int64_t loc = i - R.p_off;
+    int lb = (int)(loc / R.bcap);
+    if (lb >= R.nbrick || loc - (int64_t)lb * R.bcap >= B.bcnt[0][R.b_off + lb]) return;
     double F[3], v[3], x[3];
     for (int a = 0; a < 3; ++a) {
-        F[a] = B.Fst[a * ntot + i];
-        v[a] = B.v[a * ntot + i];
-        x[a] = B.x[cur][a * ntot + i];
+        F[a] = B.Fst[a * S_ + i];
+        v[a] = B.v[a * S_ + i];
+        x[a] = B.x[cur][a * S_ + i];
     }
     integrate_one(st, MODE_MID, true, F, v, x, st.seed, (uint64_t)B.tag[i],
                   B.step[r] + st.step_off);
     double d2 = 0.0;
     for (int a = 0; a < 3; ++a) {
-        B.v[a * ntot + i] = v[a];
-        B.x[cur ^ 1][a * ntot + i] = x[a];
-        double dd = x[a] - B.xref[a * ntot + i];
+        B.v[a * S_ + i] = v[a];
+        B.x[cur ^ 1][a * S_ + i] = x[a];
+        double dd = x[a] - B.xref[a * S_ + i];
         d2 += dd * dd;
     }
     if (d2 > R.disp2) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
@@ -1106,7 +1276,6 @@ __global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
     const RepDev &R = B.reps[r];
     __shared__ double red[8][1024 / VBC_WAVE];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // fixed assignment of bricks to threads, then a fixed-order combine
     for (int b = threadIdx.x; b < R.nbrick; b += blockDim.x)
         for (int k = 0; k < 8; ++k) acc[k] += B.part[(size_t)(R.b_off + b) * 8 + k];
     int wv = threadIdx.x / VBC_WAVE, ln = threadIdx.x % VBC_WAVE;
@@ -1122,32 +1291,33 @@ __global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
     }
 }
 
-// Export the list of one replica as tag pairs.
+// Export the list of one replica as tag pairs (inspection and tests).
 __global__ void k_export_nlist(Buffers B, Launch P, int rep, int32_t *__restrict__ pairs,
                                int64_t cap, unsigned long long *__restrict__ count)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
-    int b = blockIdx.x;
     const RepDev &R = B.reps[rep];
-    if (b >= R.nbrick) return;
+    int lb = blockIdx.x;
+    if (lb >= R.nbrick) return;
+    int b = R.b_off + lb;
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs T = carve_tabs(smem, nh_cap);
-    stage_tables(R, b, B, S, T, 1 << 30);
+    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
+                 1 << 30);
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.own_start + t;
-        int nn = B.nn[i];
-        for (int s = 0; s < nn; ++s) {
-            int u = B.nl[(size_t)s * P.ntot + i];
-            int64_t src;
-            int w;
-            stage_source(S, T, u, src, w);
+        int64_t i = S.base + t;
+        for_each_neighbour(B.nl, P.nslots, i, B.nn[i], [&](int u) {
+            int src = -1;
+            for (int q = 0; q < S.nh; ++q)
+                if (u >= T.q_off[q] && u < T.q_off[q] + T.q_cnt[q])
+                    src = T.q_src[q] + (u - T.q_off[q]);
             unsigned long long k = atomicAdd(count, 1ull);
             if ((int64_t)k < cap) {
                 pairs[2 * k] = B.tag[i];
-                pairs[2 * k + 1] = B.tag[src];
+                pairs[2 * k + 1] = src >= 0 ? B.tag[src] : -1;
             }
-        }
+        });
     }
 }
 
@@ -1166,7 +1336,13 @@ static size_t tabs_bytes(const Launch &P)
     return ((size_t)5 * nh_cap * sizeof(int) + 31) & ~(size_t)31;
 }
 
-size_t lds_bytes_nlist(const Launch &P) { return tabs_bytes(P) + (size_t)P.stage_cap * 24; }
+static size_t sort_bytes(const Launch &P)
+{
+    return (size_t)4 * P.bcap_max * sizeof(int) + (size_t)3 * P.ncb_max * sizeof(int);
+}
+
+size_t lds_bytes_sort(const Launch &P) { return tabs_bytes(P) + sort_bytes(P); }
+size_t lds_bytes_nlist(const Launch &P) { return tabs_bytes(P) + (size_t)P.stage_cap * 20; }
 size_t lds_bytes_count(const Launch &P)
 {
     return tabs_bytes(P) + (size_t)P.stage_cap * (P.precision == VBC_FP64 ? 32 : 16);
@@ -1180,40 +1356,47 @@ size_t lds_bytes_force(const Launch &P)
     return tabs_bytes(P) + (size_t)P.stage_cap * (P.precision == VBC_FP64 ? 48 : 24);
 }
 
-hipError_t launch_set_state(const Buffers &B, const Launch &P, int rep_lo, int rep_hi,
-                            const double *x, const double *v, const int32_t *type,
-                            uint64_t step0, hipStream_t s, int64_t n_in, int64_t in_off)
+hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, const double *x,
+                            const double *v, const int32_t *type, uint64_t step0, hipStream_t s,
+                            int64_t n_in, int64_t in_off)
 {
     if (n_in <= 0) return hipSuccess;
-    k_set_state<<<blocks_for(n_in, 256), 256, 0, s>>>(B, P.nrep, P.ntot, rep_lo, rep_hi, in_off,
-                                                       n_in, x, v, type, step0);
+    k_set_state<<<blocks_for(n_in, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, in_off, n_in, x, v,
+                                                       type, step0);
     return hipGetLastError();
 }
 
-hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int rep_lo, int rep_hi,
-                            double *x, double *v, hipStream_t s, int64_t n_out, int64_t out_off)
+hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int64_t slot_lo,
+                            int64_t nslot, int64_t out_off, int64_t out_stride, double *x,
+                            double *v, hipStream_t s)
 {
-    if (n_out <= 0) return hipSuccess;
-    k_get_state<<<blocks_for(n_out, 256), 256, 0, s>>>(B, P.nrep, P.ntot, cur, rep_lo, rep_hi,
-                                                        out_off, n_out, x, v);
+    if (nslot <= 0) return hipSuccess;
+    k_get_state<<<blocks_for(nslot, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, slot_lo, nslot,
+                                                        out_off, out_stride, x, v);
     return hipGetLastError();
 }
 
 hipError_t launch_flags(const Buffers &B, const Launch &P, uint32_t bits, bool set, hipStream_t s)
 {
-    if (set)
-        k_flags_or<<<blocks_for(P.nrep, 64), 64, 0, s>>>(B, P.nrep, bits);
-    else
-        k_flags_clear<<<blocks_for(P.nrep, 64), 64, 0, s>>>(B, P.nrep, bits);
+    k_flags<<<blocks_for(P.nrep, 64), 64, 0, s>>>(B, P.nrep, bits, set ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Replicas flagged FULL are binned and sorted from caller-order input; replicas with a
+// pending displacement rebuild take the incremental path in the same pass (k_resort skips
+// FULL replicas, k_gbin / k_gsort skip the others), so one k_nlist serves both.
+hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, hipStream_t s)
+{
+    k_gbin<<<blocks_for(P.ntot, 256), 256, 0, s>>>(B, P.nrep, P.nslots, P.ntot, cur);
+    k_gsort<<<brick_grid(P.nbrick_tot), P.block, sort_bytes(P), s>>>(B, P, cur);
+    k_resort<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
+    k_nlist<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
     return hipGetLastError();
 }
 
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    k_bin<<<blocks_for(P.ntot, 256), 256, 0, s>>>(B, P.nrep, P.ntot, cur);
-    k_scan<<<P.nrep, 1024, 0, s>>>(B, P.nrep);
-    k_scatter<<<blocks_for(P.ntot, 256), 256, 0, s>>>(B, P.nrep, P.ntot);
-    k_cellsort<<<blocks_for(P.ncell_tot, 128), 128, 0, s>>>(B, P.nrep, P.ntot, P.ncell_tot, cur);
+    k_resort<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
     k_nlist<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
     return hipGetLastError();
 }
@@ -1283,7 +1466,7 @@ hipError_t launch_reduce(const Buffers &B, const Launch &P, double *UW, hipStrea
 hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const StepArgs &st,
                              hipStream_t s)
 {
-    k_kick_drift<<<blocks_for(P.ntot, 256), 256, 0, s>>>(B, P.nrep, P.ntot, cur, st);
+    k_kick_drift<<<blocks_for(P.nslots, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, st);
     return hipGetLastError();
 }
 

@@ -19,14 +19,15 @@ VBC_OK, VBC_ERR_ARG, VBC_ERR_BOX, VBC_ERR_NLIST_OVERFLOW, VBC_ERR_NONFINITE, VBC
 STATUS_NAMES = {0: "VBC_OK", 1: "VBC_ERR_ARG", 2: "VBC_ERR_BOX", 3: "VBC_ERR_NLIST_OVERFLOW",
                 4: "VBC_ERR_NONFINITE", 5: "VBC_ERR_HIP", 6: "VBC_ERR_CAPACITY",
                 7: "VBC_ERR_UNIMPLEMENTED", 8: "VBC_ERR_STATE"}
-FLAG_REBUILD, FLAG_NLIST_OVERFLOW, FLAG_STAGE_OVERFLOW, FLAG_NONFINITE = 1, 2, 4, 8
+FLAG_REBUILD, FLAG_NLIST_OVERFLOW, FLAG_STAGE_OVERFLOW, FLAG_NONFINITE, FLAG_LOST = 1, 2, 4, 8, 16
 FP64, FP32_MIXED = 0, 1
 NVE, LANGEVIN = 0, 1
 
 # every symbol include/vbc.h declares
 EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", "vbc_set_state",
            "vbc_get_state", "vbc_build_nlist", "vbc_count", "vbc_force", "vbc_step", "vbc_check",
-           "vbc_get_nlist", "vbc_get_options")
+           "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read")
+KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
 class PairParams(C.Structure):
@@ -48,6 +49,11 @@ class Options(C.Structure):
 class Integrator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("kT", C.c_double),
                 ("gamma", C.c_double), ("seed", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("builds", C.c_uint64), ("list_entries", C.c_uint64), ("pair_evals", C.c_uint64),
+                ("evals", C.c_uint64)]
 
 
 class VBCError(RuntimeError):
@@ -80,6 +86,9 @@ def lib():
             "vbc_check": [vp, vp, C.POINTER(C.c_uint32)],
             "vbc_get_nlist": [vp, i32, dp, i64, dp, vp],
             "vbc_get_options": [vp, C.POINTER(Options)],
+            "vbc_get_stats": [vp, vp, C.POINTER(Stats)],
+            "vbc_profile": [vp, i32, i32],
+            "vbc_profile_read": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -277,6 +286,21 @@ class System:
         if raise_on_error:
             self._ok(st)
         return st, [int(f) for f in flags]
+
+    def stats(self):
+        out = (Stats * self.nrep)()
+        self._ok(lib().vbc_get_stats(self.h, self._stream(), out))
+        return [dict(builds=o.builds, list_entries=o.list_entries, pair_evals=o.pair_evals,
+                     evals=o.evals) for o in out]
+
+    def profile(self, enable=True, max_launches=4096):
+        self._ok(lib().vbc_profile(self.h, 1 if enable else 0, int(max_launches)))
+
+    def profile_read(self):
+        ms = (C.c_double * 6)()
+        n = (C.c_int64 * 6)()
+        self._ok(lib().vbc_profile_read(self.h, self._stream(), ms, n))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def nlist_pairs(self, rep=0, cap=None):
         torch = self.torch
