@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one 512 MiB device-to-device copy (reference for byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -210,6 +212,12 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        a = torch.empty(64 * 2**20, dtype=torch.int64, device="cuda")
+        b = torch.ones_like(a)
+        torch.cuda.synchronize()
+        a.copy_(b)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -68,7 +68,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t o_reps, o_cell_rank, o_brick_rank0, o_cstart0, o_cstart1, o_ccnt0, o_ccnt1, o_bcnt0,
         o_bcnt1, o_bfill, o_x0, o_x1, o_v, o_Fst, o_xref, o_tag, o_type, o_lcell, o_xs, o_vs,
-        o_tags, o_types, o_lcells, o_src, o_inv, o_nl, o_nn, o_nd, o_sA, o_win, o_part, o_flags,
+        o_tags, o_types, o_lcells, o_src, o_inv, o_smap, o_wmap, o_stotal, o_nl, o_nn, o_nd, o_sA, o_win, o_part, o_flags,
         o_step, o_stats, o_bevals, o_bentries;
 };
 
@@ -147,8 +147,8 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
     if (opt.block != 0 && (opt.block < 64 || opt.block > 1024 || opt.block % 64))
         return fail(VBC_ERR_ARG, "block must be a multiple of 64 in 64..1024");
     if (opt.k_max < 0 || opt.k_max > 65528) return fail(VBC_ERR_ARG, "k_max must be 0..65528");
-    if (opt.stage_cap < 0 || opt.stage_cap > 65535)
-        return fail(VBC_ERR_ARG, "stage_cap must be 0..65535");
+    if (opt.stage_cap < 0 || opt.stage_cap > 65534)
+        return fail(VBC_ERR_ARG, "stage_cap must be 0..65534");
 
     Launch &P = Lo.P;
     std::memset(&P, 0, sizeof(P));
@@ -282,7 +282,7 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
         P.stage_cap = opt.stage_cap;
     } else {
         double mean = rho_cell_max * nh_max;
-        P.stage_cap = std::min(65535, round_up((int)std::ceil(mean * 1.3 + 96.0), 32));
+        P.stage_cap = std::min(65504, round_up((int)std::ceil(mean * 1.3 + 96.0), 32));
     }
     opt.k_max = P.k_max;
     opt.block = P.block;
@@ -318,6 +318,9 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
     Lo.o_lcells = carve(off, S);
     Lo.o_src = carve(off, sizeof(int32_t) * S);
     Lo.o_inv = carve(off, sizeof(int32_t) * P.ntot);
+    Lo.o_smap = carve(off, sizeof(int32_t) * (size_t)P.nbrick_tot * P.stage_cap);
+    Lo.o_wmap = carve(off, (size_t)P.nbrick_tot * P.stage_cap);
+    Lo.o_stotal = carve(off, sizeof(int32_t) * P.nbrick_tot);
     Lo.o_nl = carve(off, 16 * (size_t)P.nchunk * S);
     Lo.o_nn = carve(off, sizeof(uint16_t) * S);
     Lo.o_nd = carve(off, sizeof(double) * S);
@@ -439,6 +442,9 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
     B.lcells = at<uint8_t>(d_ws, Lo.o_lcells);
     B.src = at<int32_t>(d_ws, Lo.o_src);
     B.inv = at<int32_t>(d_ws, Lo.o_inv);
+    B.smap = at<int32_t>(d_ws, Lo.o_smap);
+    B.wmap = at<uint8_t>(d_ws, Lo.o_wmap);
+    B.stotal = at<int32_t>(d_ws, Lo.o_stotal);
     B.nl = at<uint4>(d_ws, Lo.o_nl);
     B.nn = at<uint16_t>(d_ws, Lo.o_nn);
     B.nd = at<double>(d_ws, Lo.o_nd);

@@ -82,6 +82,9 @@ struct Buffers {
     uint8_t *lcells;         // next layout
     int32_t *src;            // [nslots] full build: members of each brick (dense index)
     int32_t *inv;            // [ntot] caller index (o_off + tag) -> slot
+    int32_t *smap;           // [nbrick_tot][stage_cap] source slot of each staged particle
+    uint8_t *wmap;           // [nbrick_tot][stage_cap] packed image shift of each staged particle
+    int32_t *stotal;         // [nbrick_tot] staged particles per brick (> stage_cap: overflow)
     uint4 *nl;               // [nchunk][nslots] neighbour list chunks of 8 x uint16
     uint16_t *nn;            // [nslots] list length
     double *nd;              // [nslots] counts (FP64)

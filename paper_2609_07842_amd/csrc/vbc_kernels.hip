@@ -44,8 +44,14 @@ template <class T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
-__device__ __forceinline__ float rsqrt_r(float x) { return __frsqrt_rn(x); }
+// Pair arithmetic: the hardware square root and reciprocal square root in FP32 (<= 1 ulp),
+// the exactly rounded ones in FP64.
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float clamp01(float u) { return __builtin_amdgcn_fmed3f(u, 0.0f, 1.0f); }
+__device__ __forceinline__ double clamp01(double u) { return fmin(fmax(u, 0.0), 1.0); }
 
 template <class F>
 __device__ __forceinline__ int bsearch_last(int nrep, F key, int64_t v)
@@ -314,6 +320,28 @@ __device__ __forceinline__ void stage_copy(const StageHdr &S, const StageTabs &T
         int off = T.q_off[q], src = T.q_src[q], cnt = T.q_cnt[q], w = T.q_w[q];
         for (int k = gl; k < cnt; k += VBC_GROUP) fn(off + k, src + k, w);
     }
+}
+
+// Header of brick b for a pass over the current layout: geometry, own range and the
+// staged count recorded by the last list build (one thread).
+__device__ __forceinline__ void pass_header(const RepDev &R, const Buffers &B, int b, int lb,
+                                            int stage_cap, StageHdr &S)
+{
+    brick_geometry(R, lb, S);
+    S.n_own = B.bcnt[0][b];
+    S.total = B.stotal[b];
+    S.overflow = S.total > stage_cap;
+}
+
+// Call fn(staged_slot, source_slot, packed_shift) for every particle staged by brick b,
+// from the staging map the list build recorded: one coalesced read, no cell-table walk.
+template <class F>
+__device__ __forceinline__ void stage_map(const Buffers &B, int b, int stage_cap,
+                                          const StageHdr &S, F &&fn)
+{
+    const int32_t *sm = B.smap + (size_t)b * stage_cap;
+    const uint8_t *wm = B.wmap + (size_t)b * stage_cap;
+    for (int t = threadIdx.x; t < S.total; t += blockDim.x) fn(t, sm[t], (int)wm[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,6 +677,7 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
             if (lost_sum != (unsigned long long)R.n) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_LOST);
         }
     }
+    if (threadIdx.x == 0) B.stotal[b] = S.total;
     if (S.overflow) {
         for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) B.nn[S.base + t] = 0;
         if (threadIdx.x == 0) {
@@ -657,7 +686,11 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
         }
         return;
     }
+    int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
     stage_copy(S, T, [&](int t, int src, int w) {
+        sm[t] = src;
+        wm[t] = (uint8_t)w;
         float4 p;
         p.x = (float)((B.xs[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
         p.y = (float)((B.xs[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
@@ -726,8 +759,18 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
                         }
                     }
                 }
-        if ((nn & (CHUNK - 1)) && nn <= kmax)
+        if ((nn & (CHUNK - 1)) && nn <= kmax) {
+            // pad the last chunk with the dummy staged slot (far away: contributes nothing)
+            const uint32_t D = (uint32_t)P.stage_cap;
+            for (int e = nn & (CHUNK - 1); e < CHUNK; ++e) {
+                uint32_t hv = D << (16 * (e & 1));
+                if (e < 2) buf[0] |= hv;
+                else if (e < 4) buf[1] |= hv;
+                else if (e < 6) buf[2] |= hv;
+                else buf[3] |= hv;
+            }
             B.nl[(size_t)(nn / CHUNK) * S_ + i] = make_uint4(buf[0], buf[1], buf[2], buf[3]);
+        }
         if (nn > kmax) {
             ovf = true;
             nn = kmax;
@@ -746,8 +789,10 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
 // list sweep helper
 // ---------------------------------------------------------------------------
 
-// Visit the list of one own particle: fn(staged index) for each entry, eight entries per
-// 16-byte chunk, with the next chunk's load issued before the current one is processed.
+// Visit the list of one own particle in whole chunks of eight entries (the last chunk is
+// padded with the dummy staged slot, whose terms all vanish), with the next chunk's load
+// issued before the current one is processed.  fn(staged index) is called for every entry
+// of a chunk without a guard, so the eight LDS gathers of a chunk can be in flight together.
 template <class F>
 __device__ __forceinline__ void for_each_neighbour(const uint4 *__restrict__ nl, int64_t S_,
                                                    int64_t i, int nn, F &&fn)
@@ -758,13 +803,23 @@ __device__ __forceinline__ void for_each_neighbour(const uint4 *__restrict__ nl,
     uint4 q = lp[0];
     for (int c = 0; c < nch; ++c) {
         uint4 qn = (c + 1 < nch) ? lp[(size_t)(c + 1) * S_] : q;
-        int m = nn - c * CHUNK;
         uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int e = 0; e < CHUNK; ++e)
-            if (e < m) fn((int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu));
+        for (int e = 0; e < CHUNK; ++e) fn((int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu));
         q = qn;
     }
+}
+
+// The dummy staged slot that pads list chunks: far from every particle of the brick.
+template <class R4>
+__device__ __forceinline__ R4 dummy_pos()
+{
+    R4 p;
+    p.x = 1.0e6f;
+    p.y = 1.0e6f;
+    p.z = 1.0e6f;
+    p.w = 0;
+    return p;
 }
 
 // ---------------------------------------------------------------------------
@@ -842,17 +897,15 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
-    int nh_cap = (P.nh_max + 3) & ~3;
-    StageTabs T = carve_tabs(smem, nh_cap);
-    R4 *spos = (R4 *)after_tabs(smem, nh_cap);
+    R4 *spos = (R4 *)smem;
     const int64_t S_ = P.nslots;
     load_pairs<Real>(R, pt);
     if (threadIdx.x == 0) {
         any_win = 0;
         ev_sum = 0ull;
+        pass_header(R, B, b, lb, P.stage_cap, S);
     }
-    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
-                 P.stage_cap);
+    __syncthreads();
     R2 *sA = (R2 *)B.sA;
     if (S.overflow) {
         for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -867,9 +920,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         return;
     }
     const double *X = B.x[cur];
-    stage_copy(S, T, [&](int t, int src, int w) {
+    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
         spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
     });
+    if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<R4>();
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
@@ -879,35 +933,35 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         int64_t i = S.base + t;
         R4 pi = spos[t];
         int ti = MULTI ? (int)pi.w : 0;
-        int whole = 0, inside = 0;
-        double frac = 0.0;
+        int inside = 0;
+        double n = 0.0;
+        Real chunk = Real(0);
+        int e = 0;
+        // omega(r, r_l, r_h) = (1 - u^2)^2 with u = clamp((r - r_l)/(r_h - r_l), 0, 1): exactly 1
+        // inside r_l and 0 beyond r_h; partial sums of eight terms are added in FP64
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
             inside += (r2 < p0.rc2) ? 1 : 0;
+            Real rr = sqrt_r(r2);
             if (MULTI) {
                 int tj = (int)pj.w;
-                if (!((R.mask[ti] >> tj) & 1u)) return;
                 const PairR<Real> &q = pt[ti * MAXT + tj];
-                if (r2 <= q.rl2) {
-                    ++whole;
-                } else if (r2 < q.rh2) {
-                    Real uu = (sqrt(r2) - q.r_l) * q.inv_dw;
-                    Real qq = Real(1) - uu * uu;
-                    frac += (double)(qq * qq);
-                }
+                Real uu = clamp01((rr - q.r_l) * q.inv_dw);
+                Real qq = Real(1) - uu * uu;
+                chunk += ((R.mask[ti] >> tj) & 1u) ? qq * qq : Real(0);
             } else {
-                if (r2 <= p0.rl2) {
-                    ++whole;
-                } else if (r2 < p0.rh2) {
-                    Real uu = (sqrt(r2) - p0.r_l) * p0.inv_dw;
-                    Real qq = Real(1) - uu * uu;
-                    frac += (double)(qq * qq);
-                }
+                Real uu = clamp01((rr - p0.r_l) * p0.inv_dw);
+                Real qq = Real(1) - uu * uu;
+                chunk += qq * qq;
+            }
+            if (++e == CHUNK) {
+                n += (double)chunk;
+                chunk = Real(0);
+                e = 0;
             }
         });
-        double n = (double)whole + frac;
         evals += (unsigned long long)inside;
         B.nd[i] = n;
         if (MULTI) {
@@ -942,76 +996,94 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
 template <class Real, bool MULTI>
 __global__ void k_embed(Buffers B, Launch P, int cur)
 {
-    using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ PairR<Real> pt[MAXT * MAXT];
+    __shared__ int nw;
+    int *wl = (int *)smem;  // [bcap] own particles inside a switching window
     int b = brick_of_block();
     if (b >= P.nbrick_tot) return;
     if (!B.win[b]) return;
     int r = rep_of_brick(B.reps, P.nrep, b);
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
-    int nh_cap = (P.nh_max + 3) & ~3;
-    StageTabs T = carve_tabs(smem, nh_cap);
-    R4 *spos = (R4 *)after_tabs(smem, nh_cap);
-    Real *ss = (Real *)(spos + P.stage_cap);
     const int64_t S_ = P.nslots;
     load_pairs<Real>(R, pt);
-    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
-                 P.stage_cap);
-    if (S.overflow) return;
-    R2 *sA = (R2 *)B.sA;
-    const double *X = B.x[cur];
-    stage_copy(S, T, [&](int t, int src, int w) {
-        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
-        ss[t] = sA[src].x;
-    });
+    if (threadIdx.x == 0) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        nw = 0;
+    }
     __syncthreads();
-    const PairR<Real> p0 = pt[0];
+    if (S.overflow) return;
+    // 1. collect the brick's particles whose count lies inside a switching window
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        int64_t i = S.base + t;
-        double n_i = B.nd[i];
-        R4 pi = spos[t];
-        int ti = MULTI ? (int)pi.w : 0;
-        double sd_i = 0.0;
+        double n_i = B.nd[S.base + t];
         bool any = false;
         if (MULTI) {
+            int ti = B.type[S.base + t];
             for (int u = 0; u < R.ntypes; ++u) {
                 const PairDev &pd = R.pair[ti * MAXT + u];
                 if (pd.attract && n_i > pd.x1 && n_i < pd.x2) any = true;
             }
         } else {
-            sd_i = omega_dd64(n_i, R.pair[0].x1, R.pair[0].x2);
-            any = R.pair[0].attract && sd_i != 0.0;
+            any = R.pair[0].attract && n_i > R.pair[0].x1 && n_i < R.pair[0].x2;
         }
-        if (!any) continue;
+        if (any) wl[atomicAdd(&nw, 1)] = t;
+    }
+    __syncthreads();
+    // 2. eight lanes per window particle, one entry of each list chunk per lane; neighbours
+    //    are gathered from global memory through the brick's staging map
+    R2 *sA = (R2 *)B.sA;
+    const double *X = B.x[cur];
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
+    const PairR<Real> p0 = pt[0];
+    const int e = threadIdx.x % CHUNK;
+    const int g = threadIdx.x / CHUNK, ng = blockDim.x / CHUNK;
+    for (int k = g; k < nw; k += ng) {
+        int t = wl[k];
+        int64_t i = S.base + t;
+        double n_i = B.nd[i];
+        int ti = MULTI ? B.type[i] : 0;
+        const double xi0 = X[i], xi1 = X[S_ + i], xi2 = X[2 * S_ + i];
+        int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
-        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
-            R4 pj = spos[u];
-            Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        for (int c = 0; c < nch; ++c) {
+            uint4 q = B.nl[(size_t)c * S_ + i];
+            uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
+            int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+            if (u == P.stage_cap) continue;  // padding
+            int src = sm[u], w = wm[u];
+            Real dx = (Real)(xi0 - (X[src] + R.L[0] * (double)unpack_w(w, 0)));
+            Real dy = (Real)(xi1 - (X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)));
+            Real dz = (Real)(xi2 - (X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)));
             Real r2 = dx * dx + dy * dy + dz * dz;
             if (MULTI) {
-                int tj = (int)pj.w;
-                const PairR<Real> &q = pt[ti * MAXT + tj];
-                if (!q.attract) return;
-                Real uu = (sqrt(r2) - q.m) * q.inv_w;
+                int tj = B.type[src];
+                const PairR<Real> &q2 = pt[ti * MAXT + tj];
+                if (!q2.attract) continue;
+                Real uu = (sqrt_r(r2) - q2.m) * q2.inv_w;
                 Real qq = Real(1) - uu * uu;
-                if (!(qq > Real(0))) return;
+                if (!(qq > Real(0))) continue;
                 const PairDev &pd = R.pair[ti * MAXT + tj];
                 double sdi = omega_dd64(n_i, pd.x1, pd.x2);
-                if (sdi == 0.0) return;
-                Real sj = omega_r<Real>(ss[u], q.x1, q.x2);
-                acc += sdi * (double)(sj * (-q.E_a * qq * qq));
+                Real sj = omega_r<Real>(sA[src].x, q2.x1, q2.x2);
+                acc += sdi * (double)(sj * (-q2.E_a * qq * qq));
             } else {
-                Real uu = (sqrt(r2) - p0.m) * p0.inv_w;
+                Real uu = (sqrt_r(r2) - p0.m) * p0.inv_w;
                 Real qq = Real(1) - uu * uu;
-                if (!(qq > Real(0))) return;
-                acc += (double)(ss[u] * (-p0.E_a * qq * qq));
+                if (!(qq > Real(0))) continue;
+                acc += (double)(sA[src].x * (-p0.E_a * qq * qq));
             }
-        });
-        sA[i].y = (Real)(MULTI ? acc : sd_i * acc);
+        }
+        // fixed-order reduction over the eight lanes of the group
+#pragma unroll
+        for (int o = CHUNK / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, CHUNK);
+        if (e == 0) {
+            double A = MULTI ? acc : omega_dd64(n_i, R.pair[0].x1, R.pair[0].x2) * acc;
+            sA[i].y = (Real)A;
+        }
     }
 }
 
@@ -1058,16 +1130,16 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     int r = rep_of_brick(B.reps, P.nrep, b);
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
-    int nh_cap = (P.nh_max + 3) & ~3;
-    StageTabs T = carve_tabs(smem, nh_cap);
-    R4 *spos = (R4 *)after_tabs(smem, nh_cap);
-    R2 *ssa = (R2 *)(spos + P.stage_cap);
+    R4 *spos = (R4 *)smem;
+    R2 *ssa = (R2 *)(spos + P.stage_cap + 1);
     const int64_t S_ = P.nslots;
     const int64_t ntot = P.ntot;
     load_pairs<Real>(R, pt);
-    if (threadIdx.x == 0) moved = 0;
-    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
-                 P.stage_cap);
+    if (threadIdx.x == 0) {
+        moved = 0;
+        pass_header(R, B, b, lb, P.stage_cap, S);
+    }
+    __syncthreads();
     const R2 *sA = (const R2 *)B.sA;
     if (S.overflow) {
         if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
@@ -1075,10 +1147,14 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         return;
     }
     const double *X = B.x[cur];
-    stage_copy(S, T, [&](int t, int src, int w) {
+    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
         spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
         ssa[t] = sA[src];
     });
+    if (threadIdx.x == 0) {
+        spos[P.stage_cap] = dummy_pos<R4>();
+        ssa[P.stage_cap] = R2{Real(0), Real(0)};
+    }
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
@@ -1123,22 +1199,20 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 uc = uc < Real(0) ? Real(0) : (uc > Real(1) ? Real(1) : uc);
                 phr += asum * q.c_c * uc * (Real(1) - uc * uc) * rinv;
             } else {
-                if (!(r2 < p0.rc2)) return;
+                // branch-free: beyond every cutoff (and for the padding slot) all three terms
+                // vanish through the clamps
                 R2 saj = ssa[u];
                 Real rinv = rsqrt_r(r2 > Real(1e-30) ? r2 : Real(1e-30));
                 Real rr = r2 * rinv;
-                Real tc = Real(1) - r2 * p0.inv_rr2;
-                tc = tc > Real(0) ? tc : Real(0);
+                Real tc = fmax(Real(1) - r2 * p0.inv_rr2, Real(0));
                 phr = p0.c_r * tc;
                 ep = p0.E_r * tc * tc;
                 Real uu = (rr - p0.m) * p0.inv_w;
-                Real qq = Real(1) - uu * uu;
-                qq = qq > Real(0) ? qq : Real(0);
+                Real qq = fmax(Real(1) - uu * uu, Real(0));
                 Real psi = sai.x * saj.x;
                 ep -= p0.E_a * psi * qq * qq;
                 phr += psi * p0.c_a * uu * qq * rinv;
-                Real uc = (rr - p0.r_l) * p0.inv_dw;
-                uc = uc < Real(0) ? Real(0) : (uc > Real(1) ? Real(1) : uc);
+                Real uc = clamp01((rr - p0.r_l) * p0.inv_dw);
                 phr += (sai.y + saj.y) * p0.c_c * uc * (Real(1) - uc * uc) * rinv;
             }
             fx -= phr * dx;
@@ -1295,27 +1369,23 @@ __global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
 __global__ void k_export_nlist(Buffers B, Launch P, int rep, int32_t *__restrict__ pairs,
                                int64_t cap, unsigned long long *__restrict__ count)
 {
-    extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     const RepDev &R = B.reps[rep];
     int lb = blockIdx.x;
     if (lb >= R.nbrick) return;
     int b = R.b_off + lb;
-    int nh_cap = (P.nh_max + 3) & ~3;
-    StageTabs T = carve_tabs(smem, nh_cap);
-    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, T,
-                 1 << 30);
+    if (threadIdx.x == 0) pass_header(R, B, b, lb, P.stage_cap, S);
+    __syncthreads();
+    if (S.overflow) return;
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
         for_each_neighbour(B.nl, P.nslots, i, B.nn[i], [&](int u) {
-            int src = -1;
-            for (int q = 0; q < S.nh; ++q)
-                if (u >= T.q_off[q] && u < T.q_off[q] + T.q_cnt[q])
-                    src = T.q_src[q] + (u - T.q_off[q]);
+            if (u == P.stage_cap) return;  // padding
             unsigned long long k = atomicAdd(count, 1ull);
             if ((int64_t)k < cap) {
                 pairs[2 * k] = B.tag[i];
-                pairs[2 * k + 1] = src >= 0 ? B.tag[src] : -1;
+                pairs[2 * k + 1] = B.tag[sm[u]];
             }
         });
     }
@@ -1345,15 +1415,12 @@ size_t lds_bytes_sort(const Launch &P) { return tabs_bytes(P) + sort_bytes(P); }
 size_t lds_bytes_nlist(const Launch &P) { return tabs_bytes(P) + (size_t)P.stage_cap * 20; }
 size_t lds_bytes_count(const Launch &P)
 {
-    return tabs_bytes(P) + (size_t)P.stage_cap * (P.precision == VBC_FP64 ? 32 : 16);
+    return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : 16);
 }
-size_t lds_bytes_embed(const Launch &P)
-{
-    return tabs_bytes(P) + (size_t)P.stage_cap * (P.precision == VBC_FP64 ? 40 : 20);
-}
+size_t lds_bytes_embed(const Launch &P) { return (size_t)P.bcap_max * sizeof(int); }
 size_t lds_bytes_force(const Launch &P)
 {
-    return tabs_bytes(P) + (size_t)P.stage_cap * (P.precision == VBC_FP64 ? 48 : 24);
+    return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 48 : 24);
 }
 
 hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, const double *x,
@@ -1418,15 +1485,16 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
 
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    size_t lds = lds_bytes_embed(P);
     unsigned g = brick_grid(P.nbrick_tot);
     bool multi = P.ntypes_max > 1;
+    const int bs = 256;
+    size_t lds = lds_bytes_embed(P);
     if (P.precision == VBC_FP64) {
-        if (multi) k_embed<double, true><<<g, P.block, lds, s>>>(B, P, cur);
-        else k_embed<double, false><<<g, P.block, lds, s>>>(B, P, cur);
+        if (multi) k_embed<double, true><<<g, bs, lds, s>>>(B, P, cur);
+        else k_embed<double, false><<<g, bs, lds, s>>>(B, P, cur);
     } else {
-        if (multi) k_embed<float, true><<<g, P.block, lds, s>>>(B, P, cur);
-        else k_embed<float, false><<<g, P.block, lds, s>>>(B, P, cur);
+        if (multi) k_embed<float, true><<<g, bs, lds, s>>>(B, P, cur);
+        else k_embed<float, false><<<g, bs, lds, s>>>(B, P, cur);
     }
     return hipGetLastError();
 }
@@ -1482,7 +1550,7 @@ hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int n
     unsigned long long *c = (unsigned long long *)count;
     k_zero_u64<<<1, 1, 0, s>>>(c);
     if (nbrick > 0)
-        k_export_nlist<<<nbrick, P.block, tabs_bytes(P), s>>>(B, P, rep, pairs, cap, c);
+        k_export_nlist<<<nbrick, P.block, 0, s>>>(B, P, rep, pairs, cap, c);
     return hipGetLastError();
 }
 
