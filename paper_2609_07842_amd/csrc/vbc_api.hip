@@ -29,13 +29,24 @@ struct vbc_handle_s {
     int prof_max = 0;
     std::vector<hipEvent_t> ev[VBC_NK][2];
     int prof_n[VBC_NK] = {0, 0, 0, 0, 0, 0};
+    // captured step graphs: GRAPH_STEPS mid-call steps starting from position buffer c
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    StepArgs gst[2];
+    bool use_graphs = true;
     ~vbc_handle_s()
     {
         for (int k = 0; k < VBC_NK; ++k)
             for (int e = 0; e < 2; ++e)
                 for (hipEvent_t x : ev[k][e]) (void)hipEventDestroy(x);
+        for (int c = 0; c < 2; ++c)
+            if (gexec[c]) (void)hipGraphExecDestroy(gexec[c]);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
+
+// Steps per captured graph (even, so that a replay ends on the buffer it started from).
+static constexpr int GRAPH_STEPS = 8;
 
 // Record the launch(es) of one kernel class between two events when timing is on.
 template <class Fn>
@@ -555,7 +566,7 @@ vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
     if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
     VBC_LAYOUT(h, s);
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, 0, s); }), "count");
     return VBC_OK;
 }
 
@@ -571,7 +582,7 @@ static vbc_status eval_forces(vbc_handle h, bool thermo, const StepArgs &st, dou
                               hipStream_t s)
 {
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 0, s); }), "count");
     VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
     VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
                 return launch_force(h->B, h->P, h->cur, MODE_EVAL, thermo, st, d_F, d_e, s);
@@ -593,6 +604,61 @@ vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipSt
                 "reduce");
     h->f_valid = true;
     return VBC_OK;
+}
+
+// One mid-call step (list rebuild when due, count, dU/dn, force with the closing kick of
+// this step and the opening of the next) from position buffer c, on stream s.
+static hipError_t launch_mid_step(vbc_handle h, int c, const StepArgs &st, hipStream_t s)
+{
+    hipError_t e = launch_rebuild(h->B, h->P, c, s);
+    if (e == hipSuccess) e = launch_count(h->B, h->P, c, nullptr, 1, s);
+    if (e == hipSuccess) e = launch_embed(h->B, h->P, c, s);
+    if (e == hipSuccess) e = launch_force(h->B, h->P, c, MODE_MID, false, st, nullptr, nullptr, s);
+    return e;
+}
+
+static bool same_step_args(const StepArgs &a, const StepArgs &b)
+{
+    return a.kind == b.kind && a.dt == b.dt && a.hdt == b.hdt && a.c1 == b.c1 && a.c2s == b.c2s &&
+           a.seed == b.seed;
+}
+
+// Graph of GRAPH_STEPS mid-call steps starting from buffer c, captured once per integrator
+// setting on a private stream and launched on the caller's stream.  It holds kernel nodes
+// only; every data-dependent choice (rebuild or not) is taken on the GPU.
+static hipError_t step_graph(vbc_handle h, int c, const StepArgs &st, hipGraphExec_t *out)
+{
+    if (h->gexec[c] && same_step_args(h->gst[c], st)) {
+        *out = h->gexec[c];
+        return hipSuccess;
+    }
+    if (h->gexec[c]) {
+        (void)hipGraphExecDestroy(h->gexec[c]);
+        h->gexec[c] = nullptr;
+    }
+    hipError_t e = hipSuccess;
+    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    int cc = c;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k) {
+        le = launch_mid_step(h, cc, st, h->cap_stream);
+        cc ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[c], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec[c] = nullptr;
+        return e;
+    }
+    h->gst[c] = st;
+    *out = h->gexec[c];
+    return hipSuccess;
 }
 
 vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s)
@@ -620,23 +686,35 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
         vbc_status r = eval_forces(h, false, st, nullptr, nullptr, s);
         if (r != VBC_OK) return r;
     }
-    st.step_off = 0;
+    // opening half-kick and drift of the first step, from the stored forces
     VBC_TRY(h, timed(h, VBC_K_KICK, s, [&] { return launch_kick_drift(h->B, h->P, h->cur, st, s); }), "kick");
     h->cur ^= 1;
-    for (int k = 0; k < nsteps; ++k) {
+    // nsteps - 1 mid-call steps: whole graphs, then single steps; kernel timing needs the
+    // individual launches, so it bypasses the graphs
+    int mid = nsteps - 1;
+    if (h->use_graphs && !h->prof && mid >= GRAPH_STEPS) {
+        hipGraphExec_t ge = nullptr;
+        VBC_TRY(h, step_graph(h, h->cur, st, &ge), "step graph");
+        for (; mid >= GRAPH_STEPS; mid -= GRAPH_STEPS) VBC_TRY(h, hipGraphLaunch(ge, s), "graph launch");
+    }
+    for (; mid > 0; --mid) {
         VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-        VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, s); }), "count");
+        VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 1, s); }), "count");
         VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
-        bool last = (k == nsteps - 1);
-        st.step_off = (uint64_t)k + 1;
         VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
-                    return launch_force(h->B, h->P, h->cur, last ? MODE_LAST : MODE_MID, false, st,
-                                        nullptr, nullptr, s);
+                    return launch_force(h->B, h->P, h->cur, MODE_MID, false, st, nullptr, nullptr, s);
                 }),
                 "force");
-        if (!last) h->cur ^= 1;
+        h->cur ^= 1;
     }
-    VBC_TRY(h, launch_advance(h->B, h->P, (uint64_t)nsteps, s), "advance");
+    // last step: closing half-kick only; its forces are kept for the next call
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 1, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
+    VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
+                return launch_force(h->B, h->P, h->cur, MODE_LAST, false, st, nullptr, nullptr, s);
+            }),
+            "force");
     h->f_valid = true;
     return VBC_OK;
 }

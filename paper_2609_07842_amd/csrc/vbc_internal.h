@@ -128,7 +128,6 @@ struct StepArgs {
     double dt, hdt;
     double c1, c2s;         // Langevin O-step coefficients
     uint64_t seed;
-    uint64_t step_off;      // added to the per-replica step counter
 };
 
 // host-side launchers (vbc_kernels.hip)
@@ -141,14 +140,14 @@ hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int64_t 
 hipError_t launch_flags(const Buffers &B, const Launch &P, uint32_t bits, bool set, hipStream_t s);
 hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s);
-hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, hipStream_t s);
+hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
+                        hipStream_t s);
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, bool thermo,
                         const StepArgs &st, double *F_out, double *e_out, hipStream_t s);
 hipError_t launch_reduce(const Buffers &B, const Launch &P, double *UW, hipStream_t s);
 hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const StepArgs &st,
                              hipStream_t s);
-hipError_t launch_advance(const Buffers &B, const Launch &P, uint64_t nsteps, hipStream_t s);
 hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int nbrick,
                                int32_t *pairs, int64_t cap, int64_t *count, hipStream_t s);
 size_t lds_bytes_sort(const Launch &P);

@@ -401,12 +401,6 @@ __global__ void k_flags(Buffers B, int nrep, uint32_t bits, int set)
     if (set) B.flags[r] |= bits; else B.flags[r] &= ~bits;
 }
 
-__global__ void k_advance(Buffers B, int nrep, uint64_t nsteps)
-{
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrep) B.step[r] += nsteps;
-}
-
 // ---------------------------------------------------------------------------
 // list build, step 1: the next sorted layout
 // ---------------------------------------------------------------------------
@@ -882,7 +876,7 @@ __device__ __forceinline__ void load_pairs(const RepDev &R, PairR<Real> *pt)
 }
 
 template <class Real, bool MULTI>
-__global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out)
+__global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance)
 {
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
@@ -985,7 +979,12 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     if (threadIdx.x == 0) {
         B.win[b] = (uint8_t)any_win;
         B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
-        if (lb == 0) B.stats[4 * r + 3] += 1ull;
+        if (lb == 0) {
+            B.stats[4 * r + 3] += 1ull;
+            // in a time step the count pass opens the step: the step counter (the noise
+            // counter of the Langevin O-step that the following force pass starts) advances
+            if (advance) B.step[r] += 1ull;
+        }
     }
 }
 
@@ -1158,7 +1157,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
-    const uint64_t step = B.step[r] + st.step_off;
+    const uint64_t step = B.step[r];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
     bool bad = false, mv = false;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -1331,8 +1330,7 @@ __global__ void k_kick_drift(Buffers B, int nrep, int64_t S_, int cur, StepArgs 
         v[a] = B.v[a * S_ + i];
         x[a] = B.x[cur][a * S_ + i];
     }
-    integrate_one(st, MODE_MID, true, F, v, x, st.seed, (uint64_t)B.tag[i],
-                  B.step[r] + st.step_off);
+    integrate_one(st, MODE_MID, true, F, v, x, st.seed, (uint64_t)B.tag[i], B.step[r]);
     double d2 = 0.0;
     for (int a = 0; a < 3; ++a) {
         B.v[a * S_ + i] = v[a];
@@ -1468,17 +1466,18 @@ hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, hipStream_t s)
+hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
+                        hipStream_t s)
 {
     size_t lds = lds_bytes_count(P);
     unsigned g = brick_grid(P.nbrick_tot);
     bool multi = P.ntypes_max > 1;
     if (P.precision == VBC_FP64) {
-        if (multi) k_count<double, true><<<g, P.block, lds, s>>>(B, P, cur, n_out);
-        else k_count<double, false><<<g, P.block, lds, s>>>(B, P, cur, n_out);
+        if (multi) k_count<double, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+        else k_count<double, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
     } else {
-        if (multi) k_count<float, true><<<g, P.block, lds, s>>>(B, P, cur, n_out);
-        else k_count<float, false><<<g, P.block, lds, s>>>(B, P, cur, n_out);
+        if (multi) k_count<float, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+        else k_count<float, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
     }
     return hipGetLastError();
 }
@@ -1535,12 +1534,6 @@ hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const S
                              hipStream_t s)
 {
     k_kick_drift<<<blocks_for(P.nslots, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_advance(const Buffers &B, const Launch &P, uint64_t nsteps, hipStream_t s)
-{
-    k_advance<<<blocks_for(P.nrep, 64), 64, 0, s>>>(B, P.nrep, nsteps);
     return hipGetLastError();
 }
 

@@ -294,7 +294,7 @@ class System:
                      evals=o.evals) for o in out]
 
     def profile(self, enable=True, max_launches=4096):
-        self._ok(lib().vbc_profile(self.h, 1 if enable else 0, int(max_launches)))
+        self._ok(lib().vbc_profile(self.h, 1 if enable else 0, int(max_launches) if enable else 0))
 
     def profile_read(self):
         ms = (C.c_double * 6)()
