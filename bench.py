@@ -53,6 +53,22 @@ def kernel_bytes(kind: str, N: int, kbar: float, precision: str) -> float:
     return float("nan")
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of this workload,
+    or None if the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_fluid_N1000000_rho0.5_f4.json")
+    src = os.path.join(ROOT, "paper_2609_07842_amd", "csrc", "vbc_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != cur or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["traffic_bytes"]
+
+
 def cpu_baseline(wl, target_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: full VBC forces of m
     particles of the N = 10^6 configuration (each needs O(N) scans for its own and its
@@ -171,7 +187,8 @@ def main():
     nbytes = kernel_bytes(dom, wl.N, main_run["kbar"], "fp32")
     achieved = nbytes / mean_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom),
                 "bytes_per_launch": nbytes, "mean_launch_us": mean_s * 1e6,
                 "timing": "HIP events around every launch in a second timed region of the same "
                           "K steps (individual launches instead of step graphs)",
@@ -227,11 +244,21 @@ def main():
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:
+        # reference traffic for the byte counters: 512 MiB read + 512 MiB written by HIP's
+        # own device-to-device copy kernel, then by torch's copy kernel
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
         a = torch.empty(64 * 2**20, dtype=torch.int64, device="cuda")
         b = torch.ones_like(a)
         torch.cuda.synchronize()
-        a.copy_(b)
+        hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.c_void_p]
+        rc = hip.hipMemcpyAsync(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                a.numel() * 8, 3, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": a.numel() * 8, "hipMemcpyAsync_rc": rc}), file=sys.stderr)
 
 
 if __name__ == "__main__":
