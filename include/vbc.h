@@ -17,16 +17,20 @@
  *  - "Device" pointers are HIP device memory owned by the caller.  The library allocates
  *    no device memory at all: all of its state lives in the caller-provided workspace
  *    (size from vbc_workspace_size), which must stay alive until vbc_destroy.
- *  - Calls that take a hipStream_t are asynchronous on that stream and launch only
- *    kernels (no allocation, no host synchronisation, no memset nodes), so they may be
- *    captured into a HIP graph.  Conditions detected on the GPU (list or staging
+ *  - Calls that take a hipStream_t are asynchronous on that stream.  The set-up and
+ *    read-back calls (vbc_create, vbc_pool_create, vbc_check, vbc_get_stats,
+ *    vbc_profile_read, vbc_stamps, vbc_stamps_read) synchronise or clear memory with
+ *    copies; vbc_admit uploads a descriptor with one host-to-device copy; the others
+ *    launch kernels only.  Conditions detected on the GPU (list or staging
  *    overflow, non-finite coordinates) are latched per replica in the workspace and
  *    reported by vbc_check, which synchronises the stream.
- *  - Per-particle caller arrays are structure-of-arrays over the concatenation of all
- *    replicas in replica order ("caller order"): replica r occupies indices
- *    [o_r, o_r + N_r) with o_r = N_0 + ... + N_{r-1}; inside a replica, index = tag,
- *    the particle's position in the arrays given to vbc_set_state.  A 3-vector array
- *    holds all x components, then all y, then all z (stride Ntot = sum of N_r).
+ *  - Per-particle caller arrays are structure-of-arrays over "caller order": replica r
+ *    occupies indices [o_r, o_r + N_r); inside a replica, index = tag, the particle's
+ *    position in the arrays given to vbc_set_state or vbc_admit.  A 3-vector array holds
+ *    all x components, then all y, then all z, with stride Ntot.  For a handle made by
+ *    vbc_create, o_r = N_0 + ... + N_{r-1} and Ntot = sum of N_r; for a pool
+ *    (vbc_pool_create), Ntot = max_particles and o_r comes from vbc_replica_info.
+ *  - Calls on one handle must be ordered: issue them on one stream, or synchronise.
  *  - Units: unit masses; energies in the units of E_r, E_a; kT in the same units.
  */
 #ifndef VBC_H
@@ -88,6 +92,8 @@ typedef struct {
     int32_t chain_len;              /* > 1: tags form chains of this many consecutive beads
                                        joined by harmonic bonds; 0 = no bonds */
     double k_bond, r0_bond;         /* bond energy k/2 (r - r0)^2 */
+    uint64_t seed;                  /* added (mod 2^64) to the integrator's seed to give this
+                                       replica's Langevin noise key */
 } vbc_replica_desc;
 
 /* Layout and launch knobs (0 = automatic).  None of them changes a result beyond the
@@ -104,7 +110,8 @@ typedef struct {
 enum { VBC_NVE = 0, VBC_LANGEVIN = 1 };
 
 /* Integrator.  NVE: velocity Verlet.  LANGEVIN: BAOAB splitting with friction gamma at
- * temperature kT; noise from Philox4x64-10 keyed by (seed, tag), counter (step, 0, 0, 0),
+ * temperature kT; noise from Philox4x64-10 keyed by (seed + replica seed, tag), counter
+ * (step, 0, 0, 0),
  * each of the first three words mapped to sqrt(3) (2u - 1), u = (word >> 11) 2^-53. */
 typedef struct {
     int32_t kind;
@@ -127,15 +134,18 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
 vbc_status vbc_destroy(vbc_handle h);
 const char *vbc_last_error(vbc_handle h);
 
-/* Copy positions (device, 3 x N SoA, caller order; any real values, wrapped into the box),
- * velocities (device, same layout, or NULL for zero) and types (device int32 [N], or NULL
- * for type 0) of replica rep (or of all replicas if rep < 0, then N = Ntot) into the
- * library, reset that replica's step counter to step0 and mark its list stale. */
+/* Copy positions (device, 3 x N SoA with N = N_rep; any real values, wrapped into the
+ * box), velocities (device, same layout, or NULL for zero) and types (device int32 [N], or
+ * NULL for type 0) of replica rep into the library, reset its step counter to step0 and
+ * mark its list stale.  rep < 0: every live replica, from caller-order arrays (stride
+ * Ntot).  The other replicas are left untouched: their next steps give the same results
+ * as without this call. */
 vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const double *d_v,
                          const int32_t *d_type, uint64_t step0, hipStream_t s);
 
-/* Copy positions (wrapped into [0, L)) and velocities of replica rep (or all if rep < 0)
- * out in caller order.  Either pointer may be NULL. */
+/* Copy positions (wrapped into [0, L)) and velocities of replica rep (3 x N_rep SoA) or,
+ * if rep < 0, of every live replica (caller order, stride Ntot) out.  Either pointer may
+ * be NULL. */
 vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hipStream_t s);
 
 /* Neighbour-list build (Section 5: list at the largest cutoff plus a buffer): wrap
@@ -156,11 +166,16 @@ vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s);
  * each pointer may be NULL. */
 vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipStream_t s);
 
-/* Advance every replica by nsteps steps of the integrator.  The list is rebuilt on the
- * GPU whenever some particle of a replica has moved more than skin/2 since the last build. */
+/* Advance every live replica by nsteps steps of the integrator.  The list is rebuilt on
+ * the GPU whenever some particle of a replica has moved more than skin/2 since the last
+ * build.  Replicas without stored forces (new state) get them first, each on its own,
+ * so that the others are not touched.  Calls of up to 64 steps run as one captured HIP
+ * graph launch (captured once per step count, integrator and buffer parity); longer
+ * calls replay graphs of 8 steps. */
 vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s);
 
-/* Synchronise s and report the flag word of each replica (host array [nrep], may be NULL);
+/* Synchronise s and report the flag word of each replica slot (host array [nrep] or
+ * [max_replicas], may be NULL; 0 for free slots);
  * returns the first error among them (overflow or non-finite) and clears the error bits. */
 vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica);
 
@@ -181,7 +196,7 @@ vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 typedef struct {
     uint64_t builds, list_entries, pair_evals, evals;
 } vbc_stats;
-vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out /* host [nrep] */);
+vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out /* host [slots] */);
 
 /* Kernel timing with HIP events recorded on the launch stream around every launch of each
  * kernel class, for at most max_launches launches per class (enable = 0 switches it off).
@@ -193,6 +208,78 @@ enum { VBC_K_BUILD = 0, VBC_K_COUNT = 1, VBC_K_EMBED = 2, VBC_K_FORCE = 3, VBC_K
 vbc_status vbc_profile(vbc_handle h, int32_t enable, int32_t max_launches);
 vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms /* [VBC_NK] */,
                             int64_t *launches /* [VBC_NK] */);
+
+/* ---- Replica pools: continuous batching of independent systems ------------------------
+ * A pool is a handle of fixed capacity into which replicas are admitted and from which
+ * they retire while others keep running; every launch covers the whole capacity (bricks
+ * of free or retired replicas exit at once), so the captured step graphs stay valid as the
+ * replica set changes.  The use case is the paper's own way of working: its results are
+ * sweeps over many independent state points (valency, temperature, density, well depth;
+ * Sections 3, 4 and 6), each a separate simulation. */
+
+/* Fixed capacity of a pool. */
+typedef struct {
+    int32_t max_replicas;   /* replica slots */
+    int32_t max_types;      /* 1..4 particle types per replica */
+    int64_t max_particles;  /* particles over all live replicas (caller-order index space) */
+    int64_t max_slots;      /* particle slots; a replica takes bricks x bcap of them */
+    int32_t max_bricks;     /* cell bricks (one workgroup each) */
+    int32_t max_cells;
+    int32_t max_bcap;       /* slots per brick of any replica (>= 64) */
+    int32_t chains;         /* nonzero: replicas may carry bonded chains */
+} vbc_pool_caps;
+
+/* What one replica takes from a workspace (vbc_replica_footprint). */
+typedef struct {
+    int64_t slots;          /* particle slots (bricks x bcap) */
+    int32_t bricks, cells;
+    int32_t bcap;           /* slots per brick */
+    int32_t k_max;          /* automatic list length for this replica alone */
+    int32_t stage_cap;      /* automatic staging capacity for this replica alone */
+    int32_t brick;          /* brick edge actually used (cells) */
+    size_t bytes;           /* workspace bytes it occupies with these options (k_max and
+                               stage_cap of opt, or the automatic ones if 0) */
+} vbc_footprint;
+
+/* Layout of one replica and its share of a workspace: the basis of admission by memory
+ * footprint.  No device access. */
+vbc_status vbc_replica_footprint(const vbc_replica_desc *d, const vbc_options *opt,
+                                 vbc_footprint *out);
+
+/* Bytes of device workspace for a pool.  opt->k_max and opt->stage_cap must be set (a pool
+ * has no replicas to derive them from); block defaults to 256, brick as for vbc_create. */
+vbc_status vbc_pool_workspace_size(const vbc_pool_caps *caps, const vbc_options *opt,
+                                   size_t *bytes);
+
+/* Make an empty pool in d_ws (device, >= the size above, 256-byte aligned), clearing it
+ * synchronously on s. */
+vbc_status vbc_pool_create(const vbc_pool_caps *caps, const vbc_options *opt, void *d_ws,
+                           size_t ws_bytes, hipStream_t s, vbc_handle *out);
+
+/* Admit a replica with its initial state (as vbc_set_state with rep = the new index;
+ * arrays of this replica only, stride N) and return its index in *rep.  Stream-ordered
+ * after earlier work on s; the other replicas are not touched.  VBC_ERR_CAPACITY if no
+ * slot or no contiguous range of slots, bricks, cells or particle indices is free, or if
+ * the replica needs a larger brick capacity, k_max or stage_cap than the pool has. */
+vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x,
+                     const double *d_v, const int32_t *d_type, uint64_t step0, hipStream_t s,
+                     int32_t *rep);
+
+/* Free replica rep's slot and ranges (stream-ordered: work already issued on s still sees
+ * it).  Read its state out first. */
+vbc_status vbc_retire(vbc_handle h, int32_t rep, hipStream_t s);
+
+/* Particles and caller-order offset of replica rep (0, 0 for a free slot). */
+vbc_status vbc_replica_info(vbc_handle h, int32_t rep, int64_t *n, int64_t *caller_offset);
+
+/* Step time stamps: when enabled, every step of vbc_step ends with a one-thread kernel that
+ * writes the device's constant-rate clock into a ring of 65536 entries in the workspace.
+ * vbc_stamps (re)starts the ring; vbc_stamps_read synchronises s, returns the last
+ * min(written, 65536, cap) stamps in order and the clock rate in Hz, and restarts it.
+ * Successive stamps bound each step's latency from end to end. */
+vbc_status vbc_stamps(vbc_handle h, int32_t enable, hipStream_t s);
+vbc_status vbc_stamps_read(vbc_handle h, hipStream_t s, uint64_t *out, int64_t cap, int64_t *n,
+                           double *hz);
 
 #ifdef __cplusplus
 }

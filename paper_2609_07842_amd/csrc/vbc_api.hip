@@ -1,11 +1,13 @@
-// vbc_api.hip -- host side of libvbc: parameter validation, cell/brick layout, workspace
-// carving and the order of kernel launches behind each C entry point (include/vbc.h).
+// vbc_api.hip -- host side of libvbc: parameter validation, cell/brick layout, the pool
+// allocator of the workspace and the order of kernel launches behind each C entry point
+// (include/vbc.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -14,39 +16,123 @@
 
 using namespace vbc;
 
+namespace {
+
+// First-fit allocator of contiguous index ranges [0, cap).
+struct Arena {
+    std::map<int64_t, int64_t> free;  // start -> length
+    void init(int64_t cap)
+    {
+        free.clear();
+        if (cap > 0) free[0] = cap;
+    }
+    int64_t take(int64_t n)
+    {
+        if (n <= 0) return 0;
+        for (auto it = free.begin(); it != free.end(); ++it) {
+            if (it->second < n) continue;
+            int64_t start = it->first, len = it->second;
+            free.erase(it);
+            if (len > n) free[start + n] = len - n;
+            return start;
+        }
+        return -1;
+    }
+    void give(int64_t start, int64_t n)
+    {
+        if (n <= 0) return;
+        auto it = free.emplace(start, n).first;
+        auto nx = std::next(it);
+        if (nx != free.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free.erase(nx);
+        }
+        if (it != free.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free.erase(it);
+            }
+        }
+    }
+};
+
+// Per-replica geometry and the automatic choices it implies.
+struct RepPlan {
+    RepDev R;
+    int64_t slots = 0;
+    double own_mean = 0, k_mean = 0, rho_cell = 0;
+    int nh = 1, ncb = 1;
+    int k_max_auto = 0, stage_cap_auto = 0;
+};
+
+// Fixed capacity of a workspace.
+struct Caps {
+    int32_t nrep = 0, ntypes_max = 1, any_chains = 0, bcap_max = 0, nh_max = 1, ncb_max = 1;
+    int64_t ntot = 0, nslots = 0;
+    int32_t nbrick = 0, ncell = 0;
+};
+
+struct Offsets {
+    size_t reps, brick_rep, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
+        bfill, x0, x1, v, Fst, xref, tag, type, lcell, xs, vs, tags, types, lcells, src, inv,
+        smap, wmap, stotal, nl, nn, nd, sA, win, part, flags, step, stats, bevals, bentries,
+        stamps, stamp_n;
+    size_t bytes;
+};
+
+}  // namespace
+
 struct vbc_handle_s {
-    Launch P;
+    Launch P;               // capacity-wide launch shape (all bricks)
     Buffers B;
-    std::vector<RepDev> reps;
     vbc_options opt;
+    bool pool = false;      // made by vbc_pool_create (admission checks list and staging)
+    std::vector<RepDev> reps;   // host copy of every replica slot (n == 0: free)
+    std::vector<char> live, has_state, need_full, fvalid;
+    Arena a_slot, a_brick, a_cell, a_caller;
+    RepDev *up = nullptr;       // pinned upload staging, one entry per slot
+    std::vector<hipEvent_t> up_ev;
+    std::vector<char> up_pending;
     int cur = 0;            // which position buffer holds the current positions
-    bool f_valid = false;   // Fst holds the forces of the current positions
-    bool have_state = false;
-    bool need_full = false; // unsorted input waiting for a full build
     std::string err;
     // kernel timing (vbc_profile)
     bool prof = false;
     int prof_max = 0;
     std::vector<hipEvent_t> ev[VBC_NK][2];
     int prof_n[VBC_NK] = {0, 0, 0, 0, 0, 0};
-    // captured step graphs: GRAPH_STEPS mid-call steps starting from position buffer c
+    // step time stamps (vbc_stamps)
+    bool stamps = false;
+    // captured step graphs
+    struct GraphEntry {
+        int kind, nsteps, c;
+        bool stamps;
+        StepArgs st;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    StepArgs gst[2];
     bool use_graphs = true;
     ~vbc_handle_s()
     {
         for (int k = 0; k < VBC_NK; ++k)
             for (int e = 0; e < 2; ++e)
                 for (hipEvent_t x : ev[k][e]) (void)hipEventDestroy(x);
-        for (int c = 0; c < 2; ++c)
-            if (gexec[c]) (void)hipGraphExecDestroy(gexec[c]);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (size_t r = 0; r < up_ev.size(); ++r) {
+            if (up_pending[r]) (void)hipEventSynchronize(up_ev[r]);
+            (void)hipEventDestroy(up_ev[r]);
+        }
+        if (up) (void)hipHostFree(up);
     }
 };
 
-// Steps per captured graph (even, so that a replay ends on the buffer it started from).
+// Mid-call steps per captured graph of a long call (even, so that a replay ends on the
+// buffer it started from); calls of at most CALL_GRAPH_MAX steps are captured whole.
 static constexpr int GRAPH_STEPS = 8;
+static constexpr int CALL_GRAPH_MAX = 64;
+static constexpr size_t GRAPH_CACHE = 16;
 
 // Record the launch(es) of one kernel class between two events when timing is on.
 template <class Fn>
@@ -70,21 +156,15 @@ namespace {
 
 thread_local std::string g_err;
 
-struct Layout {
-    Launch P;
-    std::vector<RepDev> reps;
-    std::vector<int32_t> cell_rank, brick_rank0;
-    vbc_options opt;
-    size_t bytes = 0;
-    // byte offsets into the workspace
-    size_t o_reps, o_cell_rank, o_brick_rank0, o_cstart0, o_cstart1, o_ccnt0, o_ccnt1, o_bcnt0,
-        o_bcnt1, o_bfill, o_x0, o_x1, o_v, o_Fst, o_xref, o_tag, o_type, o_lcell, o_xs, o_vs,
-        o_tags, o_types, o_lcells, o_src, o_inv, o_smap, o_wmap, o_stotal, o_nl, o_nn, o_nd, o_sA, o_win, o_part, o_flags,
-        o_step, o_stats, o_bevals, o_bentries;
-};
-
 vbc_status fail(vbc_status st, const std::string &msg)
 {
+    g_err = msg;
+    return st;
+}
+
+vbc_status hfail(vbc_handle h, vbc_status st, const std::string &msg)
+{
+    if (h) h->err = msg;
     g_err = msg;
     return st;
 }
@@ -146,10 +226,10 @@ size_t carve(size_t &off, size_t bytes)
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in, Layout &Lo)
+int brick_default(int precision) { return precision == VBC_FP64 ? 3 : 4; }
+
+vbc_status check_options(const vbc_options *opt_in, vbc_options &opt)
 {
-    if (!reps || nrep < 1) return fail(VBC_ERR_ARG, "need at least one replica");
-    vbc_options opt;
     std::memset(&opt, 0, sizeof(opt));
     if (opt_in) opt = *opt_in;
     if (opt.precision != VBC_FP64 && opt.precision != VBC_FP32_MIXED)
@@ -160,191 +240,189 @@ vbc_status plan(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *o
     if (opt.k_max < 0 || opt.k_max > 65528) return fail(VBC_ERR_ARG, "k_max must be 0..65528");
     if (opt.stage_cap < 0 || opt.stage_cap > 65534)
         return fail(VBC_ERR_ARG, "stage_cap must be 0..65534");
-
-    Launch &P = Lo.P;
-    std::memset(&P, 0, sizeof(P));
-    P.nrep = nrep;
-    P.precision = opt.precision;
-    int brick_target = opt.brick ? opt.brick : (opt.precision == VBC_FP64 ? 3 : 4);
-    double rho_cell_max = 0.0, k_mean_max = 0.0, own_mean_max = 0.0;
-    int64_t p_off = 0, o_off = 0;
-    int32_t c_off = 0, b_off = 0;
-    int nh_max = 1, ntypes_max = 1, any_chains = 0, bcap_max = 0, ncb_max = 1;
-    Lo.reps.resize(nrep);
-    for (int r = 0; r < nrep; ++r) {
-        const vbc_replica_desc &d = reps[r];
-        RepDev R;
-        std::memset(&R, 0, sizeof(R));
-        if (d.n < 1) return fail(VBC_ERR_ARG, "replica " + std::to_string(r) + ": n must be >= 1");
-        if (d.n > (int64_t)1 << 30) return fail(VBC_ERR_ARG, "replica too large");
-        if (d.ntypes < 1 || d.ntypes > MAXT) return fail(VBC_ERR_ARG, "ntypes must be 1..4");
-        if (!d.params) return fail(VBC_ERR_ARG, "params is NULL");
-        if (!(d.skin >= 0.0) || !std::isfinite(d.skin)) return fail(VBC_ERR_ARG, "skin must be >= 0");
-        double rc = 0.0;
-        for (int a = 0; a < d.ntypes; ++a)
-            for (int c = 0; c < d.ntypes; ++c) {
-                const vbc_pair_params &p = d.params[a * d.ntypes + c];
-                std::string why;
-                if (!pair_ok(p, why)) return fail(VBC_ERR_ARG, why);
-                if (!same_pair(p, d.params[c * d.ntypes + a]))
-                    return fail(VBC_ERR_ARG, "pair table must be symmetric");
-                rc = std::max(rc, std::max(p.r_r, std::max(p.r_a, p.r_h)));
-                R.pair[a * MAXT + c] = derive(p);
-            }
-        for (int a = 0; a < d.ntypes; ++a)
-            R.mask[a] = d.count_mask ? d.count_mask[a] : 0xFu;
-        double rl = rc + d.skin;
-        R.rc2 = rc * rc;
-        R.rlist2 = rl * rl;
-        R.disp2 = 0.25 * d.skin * d.skin;
-        int64_t ncell = 1;
-        for (int a = 0; a < 3; ++a) {
-            double L = d.L[a];
-            if (!(L > 0.0) || !std::isfinite(L)) return fail(VBC_ERR_ARG, "box edges must be > 0");
-            if (!(L > 2.0 * rl))
-                return fail(VBC_ERR_BOX, "box edge " + std::to_string(L) +
-                                             " must exceed twice the list radius " + std::to_string(rl));
-            int nc = (int)std::floor(L / rl);
-            // a cell must be at least the list radius even after rounding of x / h
-            while (nc > 1 && L / nc < rl * (1.0 + 1e-9)) --nc;
-            if (nc < 3) return fail(VBC_ERR_BOX, "fewer than 3 cells along an axis");
-            if (nc > 1023) nc = 1023;
-            R.nc[a] = nc;
-            R.L[a] = L;
-            R.h[a] = L / nc;
-            R.bd[a] = std::max(1, std::min(brick_target, nc - 2));
-            R.nb[a] = (nc + R.bd[a] - 1) / R.bd[a];
-            ncell *= nc;
-        }
-        if (ncell > (int64_t)1 << 28) return fail(VBC_ERR_ARG, "too many cells");
-        R.ncell = (int32_t)ncell;
-        R.nbrick = R.nb[0] * R.nb[1] * R.nb[2];
-        R.ntypes = d.ntypes;
-        R.chain_len = d.chain_len > 1 ? d.chain_len : 0;
-        if (R.chain_len) {
-            if (d.n % R.chain_len) return fail(VBC_ERR_ARG, "n must be a multiple of chain_len");
-            if (!(d.k_bond >= 0.0) || !(d.r0_bond >= 0.0)) return fail(VBC_ERR_ARG, "bad bond parameters");
-            if (d.r0_bond >= 0.5 * std::min(d.L[0], std::min(d.L[1], d.L[2])))
-                return fail(VBC_ERR_BOX, "bond length must be below half the box");
-            any_chains = 1;
-        }
-        R.k_bond = d.k_bond;
-        R.r0_bond = d.r0_bond;
-        // slots per brick: the mean occupancy of a full brick with room for fluctuations
-        int ncb_full = R.bd[0] * R.bd[1] * R.bd[2];
-        double per_cell = (double)d.n / (double)ncell;
-        double own_mean = per_cell * ncb_full;
-        R.bcap = std::min((int64_t)round_up((int)std::ceil(own_mean * 1.4 + 64.0), 64),
-                          std::max<int64_t>(64, d.n));
-        if ((int64_t)R.bcap * R.nbrick < d.n) R.bcap = (int32_t)((d.n + R.nbrick - 1) / R.nbrick);
-        R.p_off = p_off;
-        R.o_off = o_off;
-        R.n = d.n;
-        R.c_off = c_off;
-        R.b_off = b_off;
-        p_off += (int64_t)R.nbrick * R.bcap;
-        o_off += d.n;
-        c_off += R.ncell;
-        b_off += R.nbrick;
-        nh_max = std::max(nh_max, (R.bd[0] + 2) * (R.bd[1] + 2) * (R.bd[2] + 2));
-        ncb_max = std::max(ncb_max, ncb_full);
-        bcap_max = std::max(bcap_max, (int)R.bcap);
-        ntypes_max = std::max(ntypes_max, (int)d.ntypes);
-        double vol = d.L[0] * d.L[1] * d.L[2];
-        rho_cell_max = std::max(rho_cell_max, per_cell);
-        own_mean_max = std::max(own_mean_max, own_mean);
-        k_mean_max = std::max(k_mean_max, (double)d.n / vol * 4.18879020478639 * rl * rl * rl);
-        // static tables: brick-major ranks (x fastest inside a brick and across bricks)
-        size_t base = Lo.cell_rank.size();
-        Lo.cell_rank.resize(base + R.ncell);
-        int32_t rank = 0;
-        for (int bz = 0; bz < R.nb[2]; ++bz)
-            for (int by = 0; by < R.nb[1]; ++by)
-                for (int bx = 0; bx < R.nb[0]; ++bx) {
-                    Lo.brick_rank0.push_back(rank);
-                    int c0[3] = {bx * R.bd[0], by * R.bd[1], bz * R.bd[2]};
-                    int e[3];
-                    for (int a = 0; a < 3; ++a) e[a] = std::min(R.bd[a], R.nc[a] - c0[a]);
-                    for (int lz = 0; lz < e[2]; ++lz)
-                        for (int ly = 0; ly < e[1]; ++ly)
-                            for (int lx = 0; lx < e[0]; ++lx) {
-                                int gx = c0[0] + lx, gy = c0[1] + ly, gz = c0[2] + lz;
-                                Lo.cell_rank[base + gx + R.nc[0] * (gy + R.nc[1] * gz)] = rank++;
-                            }
-                }
-        Lo.reps[r] = R;
-    }
-    if (p_off >= ((int64_t)1 << 31) - 1) return fail(VBC_ERR_ARG, "more than 2^31 slots in total");
-    P.ntot = o_off;
-    P.nslots = p_off;
-    P.ncell_tot = c_off;
-    P.nbrick_tot = b_off;
-    P.nh_max = nh_max;
-    P.ncb_max = ncb_max;
-    P.bcap_max = bcap_max;
-    P.ntypes_max = ntypes_max;
-    P.any_chains = any_chains;
-    P.block = opt.block ? opt.block
-                        : std::max(128, std::min(512, round_up((int)std::ceil(own_mean_max), 64)));
-    P.k_max = opt.k_max ? round_up(opt.k_max, CHUNK)
-                        : std::min(65528, round_up((int)std::ceil(k_mean_max * 1.6 + 24.0), CHUNK));
-    P.nchunk = P.k_max / CHUNK;
-    if (opt.stage_cap) {
-        P.stage_cap = opt.stage_cap;
-    } else {
-        double mean = rho_cell_max * nh_max;
-        P.stage_cap = std::min(65504, round_up((int)std::ceil(mean * 1.3 + 96.0), 32));
-    }
-    opt.k_max = P.k_max;
-    opt.block = P.block;
-    opt.stage_cap = P.stage_cap;
-    opt.brick = brick_target;
-    Lo.opt = opt;
-
-    // workspace
-    size_t off = 0;
-    const int64_t S = P.nslots;
-    Lo.o_reps = carve(off, sizeof(RepDev) * nrep);
-    Lo.o_cell_rank = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_brick_rank0 = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_cstart0 = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_cstart1 = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_ccnt0 = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_ccnt1 = carve(off, sizeof(int32_t) * P.ncell_tot);
-    Lo.o_bcnt0 = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_bcnt1 = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_bfill = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_x0 = carve(off, sizeof(double) * 3 * S);
-    Lo.o_x1 = carve(off, sizeof(double) * 3 * S);
-    Lo.o_v = carve(off, sizeof(double) * 3 * S);
-    Lo.o_Fst = carve(off, sizeof(double) * 3 * S);
-    Lo.o_xref = carve(off, sizeof(double) * 3 * S);
-    Lo.o_tag = carve(off, sizeof(int32_t) * S);
-    Lo.o_type = carve(off, sizeof(int32_t) * S);
-    Lo.o_lcell = carve(off, S);
-    Lo.o_xs = carve(off, sizeof(double) * 3 * S);
-    Lo.o_vs = carve(off, sizeof(double) * 3 * S);
-    Lo.o_tags = carve(off, sizeof(int32_t) * S);
-    Lo.o_types = carve(off, sizeof(int32_t) * S);
-    Lo.o_lcells = carve(off, S);
-    Lo.o_src = carve(off, sizeof(int32_t) * S);
-    Lo.o_inv = carve(off, sizeof(int32_t) * P.ntot);
-    Lo.o_smap = carve(off, sizeof(int32_t) * (size_t)P.nbrick_tot * P.stage_cap);
-    Lo.o_wmap = carve(off, (size_t)P.nbrick_tot * P.stage_cap);
-    Lo.o_stotal = carve(off, sizeof(int32_t) * P.nbrick_tot);
-    Lo.o_nl = carve(off, 16 * (size_t)P.nchunk * S);
-    Lo.o_nn = carve(off, sizeof(uint16_t) * S);
-    Lo.o_nd = carve(off, sizeof(double) * S);
-    Lo.o_sA = carve(off, (P.precision == VBC_FP64 ? 16 : 8) * (size_t)S);
-    Lo.o_win = carve(off, P.nbrick_tot);
-    Lo.o_part = carve(off, sizeof(double) * 8 * (size_t)P.nbrick_tot);
-    Lo.o_flags = carve(off, sizeof(uint32_t) * nrep);
-    Lo.o_step = carve(off, sizeof(uint64_t) * nrep);
-    Lo.o_stats = carve(off, sizeof(unsigned long long) * 4 * nrep);
-    Lo.o_bevals = carve(off, sizeof(unsigned long long) * P.nbrick_tot);
-    Lo.o_bentries = carve(off, sizeof(uint32_t) * P.nbrick_tot);
-    Lo.bytes = off;
+    if (!opt.brick) opt.brick = brick_default(opt.precision);
     return VBC_OK;
+}
+
+int k_max_for(double k_mean) { return std::min(65528, round_up((int)std::ceil(k_mean * 1.6 + 24.0), CHUNK)); }
+int stage_cap_for(double rho_cell, int nh)
+{
+    return std::min(65504, round_up((int)std::ceil(rho_cell * nh * 1.3 + 96.0), 32));
+}
+
+// Geometry of one replica: cells of edge >= the list radius, bricks of up to brick^3 cells,
+// slots per brick, derived pair constants.
+vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, RepPlan &out)
+{
+    RepDev &R = out.R;
+    std::memset(&R, 0, sizeof(R));
+    if (d.n < 1) return fail(VBC_ERR_ARG, "n must be >= 1");
+    if (d.n > (int64_t)1 << 30) return fail(VBC_ERR_ARG, "replica too large");
+    if (d.ntypes < 1 || d.ntypes > MAXT) return fail(VBC_ERR_ARG, "ntypes must be 1..4");
+    if (!d.params) return fail(VBC_ERR_ARG, "params is NULL");
+    if (!(d.skin >= 0.0) || !std::isfinite(d.skin)) return fail(VBC_ERR_ARG, "skin must be >= 0");
+    double rc = 0.0;
+    for (int a = 0; a < d.ntypes; ++a)
+        for (int c = 0; c < d.ntypes; ++c) {
+            const vbc_pair_params &p = d.params[a * d.ntypes + c];
+            std::string why;
+            if (!pair_ok(p, why)) return fail(VBC_ERR_ARG, why);
+            if (!same_pair(p, d.params[c * d.ntypes + a]))
+                return fail(VBC_ERR_ARG, "pair table must be symmetric");
+            rc = std::max(rc, std::max(p.r_r, std::max(p.r_a, p.r_h)));
+            R.pair[a * MAXT + c] = derive(p);
+        }
+    for (int a = 0; a < d.ntypes; ++a) R.mask[a] = d.count_mask ? d.count_mask[a] : 0xFu;
+    double rl = rc + d.skin;
+    R.rc2 = rc * rc;
+    R.rlist2 = rl * rl;
+    R.disp2 = 0.25 * d.skin * d.skin;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        double L = d.L[a];
+        if (!(L > 0.0) || !std::isfinite(L)) return fail(VBC_ERR_ARG, "box edges must be > 0");
+        if (!(L > 2.0 * rl))
+            return fail(VBC_ERR_BOX, "box edge " + std::to_string(L) +
+                                         " must exceed twice the list radius " + std::to_string(rl));
+        int nc = (int)std::min(std::floor(L / rl), 4096.0);
+        // a cell must be at least the list radius even after rounding of x / h
+        while (nc > 1 && L / nc < rl * (1.0 + 1e-9)) --nc;
+        if (nc < 3) return fail(VBC_ERR_BOX, "fewer than 3 cells along an axis");
+        if (nc > 1023) nc = 1023;
+        R.nc[a] = nc;
+        R.L[a] = L;
+        R.h[a] = L / nc;
+        R.bd[a] = std::max(1, std::min(brick_target, nc - 2));
+        R.nb[a] = (nc + R.bd[a] - 1) / R.bd[a];
+        ncell *= nc;
+    }
+    if (ncell > (int64_t)1 << 28) return fail(VBC_ERR_ARG, "too many cells");
+    R.ncell = (int32_t)ncell;
+    R.nbrick = R.nb[0] * R.nb[1] * R.nb[2];
+    R.ntypes = d.ntypes;
+    R.chain_len = d.chain_len > 1 ? d.chain_len : 0;
+    if (R.chain_len) {
+        if (d.n % R.chain_len) return fail(VBC_ERR_ARG, "n must be a multiple of chain_len");
+        if (!(d.k_bond >= 0.0) || !(d.r0_bond >= 0.0)) return fail(VBC_ERR_ARG, "bad bond parameters");
+        if (d.r0_bond >= 0.5 * std::min(d.L[0], std::min(d.L[1], d.L[2])))
+            return fail(VBC_ERR_BOX, "bond length must be below half the box");
+    }
+    R.k_bond = d.k_bond;
+    R.r0_bond = d.r0_bond;
+    R.seed = d.seed;
+    R.n = d.n;
+    // slots per brick: the mean occupancy of a full brick with room for fluctuations
+    out.ncb = R.bd[0] * R.bd[1] * R.bd[2];
+    out.nh = (R.bd[0] + 2) * (R.bd[1] + 2) * (R.bd[2] + 2);
+    double per_cell = (double)d.n / (double)ncell;
+    out.own_mean = per_cell * out.ncb;
+    R.bcap = (int32_t)std::min((int64_t)round_up((int)std::ceil(out.own_mean * 1.4 + 64.0), 64),
+                               std::max<int64_t>(64, d.n));
+    if ((int64_t)R.bcap * R.nbrick < d.n) R.bcap = (int32_t)((d.n + R.nbrick - 1) / R.nbrick);
+    out.slots = (int64_t)R.nbrick * R.bcap;
+    double vol = d.L[0] * d.L[1] * d.L[2];
+    out.rho_cell = per_cell;
+    out.k_mean = (double)d.n / vol * 4.18879020478639 * rl * rl * rl;
+    out.k_max_auto = k_max_for(out.k_mean);
+    out.stage_cap_auto = stage_cap_for(out.rho_cell, out.nh);
+    return VBC_OK;
+}
+
+// Workspace layout for a capacity; every array is 256-byte aligned.
+Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
+{
+    Offsets o;
+    size_t off = 0;
+    const int64_t S = C.nslots;
+    const size_t nb = (size_t)C.nbrick, nc = (size_t)C.ncell, nr = (size_t)C.nrep;
+    o.reps = carve(off, sizeof(RepDev) * nr);
+    o.brick_rep = carve(off, sizeof(int32_t) * nb);
+    o.cell_rank = carve(off, sizeof(int32_t) * nc);
+    o.brick_rank0 = carve(off, sizeof(int32_t) * nb);
+    o.cstart0 = carve(off, sizeof(int32_t) * nc);
+    o.cstart1 = carve(off, sizeof(int32_t) * nc);
+    o.ccnt0 = carve(off, sizeof(int32_t) * nc);
+    o.ccnt1 = carve(off, sizeof(int32_t) * nc);
+    o.bcnt0 = carve(off, sizeof(int32_t) * nb);
+    o.bcnt1 = carve(off, sizeof(int32_t) * nb);
+    o.bfill = carve(off, sizeof(int32_t) * nb);
+    o.x0 = carve(off, sizeof(double) * 3 * S);
+    o.x1 = carve(off, sizeof(double) * 3 * S);
+    o.v = carve(off, sizeof(double) * 3 * S);
+    o.Fst = carve(off, sizeof(double) * 3 * S);
+    o.xref = carve(off, sizeof(double) * 3 * S);
+    o.tag = carve(off, sizeof(int32_t) * S);
+    o.type = carve(off, sizeof(int32_t) * S);
+    o.lcell = carve(off, S);
+    o.xs = carve(off, sizeof(double) * 3 * S);
+    o.vs = carve(off, sizeof(double) * 3 * S);
+    o.tags = carve(off, sizeof(int32_t) * S);
+    o.types = carve(off, sizeof(int32_t) * S);
+    o.lcells = carve(off, S);
+    o.src = carve(off, sizeof(int32_t) * S);
+    o.inv = carve(off, sizeof(int32_t) * C.ntot);
+    o.smap = carve(off, sizeof(int32_t) * nb * stage_cap);
+    o.wmap = carve(off, nb * stage_cap);
+    o.stotal = carve(off, sizeof(int32_t) * nb);
+    o.nl = carve(off, 16 * (size_t)nchunk * S);
+    o.nn = carve(off, sizeof(uint16_t) * S);
+    o.nd = carve(off, sizeof(double) * S);
+    o.sA = carve(off, (precision == VBC_FP64 ? 16 : 8) * (size_t)S);
+    o.win = carve(off, nb);
+    o.part = carve(off, sizeof(double) * 8 * nb);
+    o.flags = carve(off, sizeof(uint32_t) * nr);
+    o.step = carve(off, sizeof(uint64_t) * nr);
+    o.stats = carve(off, sizeof(unsigned long long) * 4 * nr);
+    o.bevals = carve(off, sizeof(unsigned long long) * nb);
+    o.bentries = carve(off, sizeof(uint32_t) * nb);
+    o.stamps = carve(off, sizeof(unsigned long long) * STAMP_CAP);
+    o.stamp_n = carve(off, sizeof(unsigned long long));
+    o.bytes = off;
+    return o;
+}
+
+// Bytes of the workspace that a replica occupies: its share of every per-slot, per-brick,
+// per-cell, per-particle and per-replica array of the layout above.
+size_t footprint_bytes(const RepPlan &rp, int precision, int nchunk, int stage_cap)
+{
+    size_t per_slot = 7 * 24 + 5 * 4 + 2 + 16 * (size_t)nchunk + 2 + 8 + (precision == VBC_FP64 ? 16 : 8);
+    size_t per_brick = 4 * 6 + 5 * (size_t)stage_cap + 1 + 64 + 8 + 4;
+    size_t per_cell = 5 * 4;
+    return per_slot * (size_t)rp.slots + per_brick * (size_t)rp.R.nbrick +
+           per_cell * (size_t)rp.R.ncell + 4 * (size_t)rp.R.n + sizeof(RepDev) + 4 + 8 + 32;
+}
+
+// Launch shape and LDS bounds for a capacity.
+Launch launch_for(const Caps &C, const vbc_options &opt)
+{
+    Launch P;
+    std::memset(&P, 0, sizeof(P));
+    P.nrep = C.nrep;
+    P.ntot = C.ntot;
+    P.nslots = C.nslots;
+    P.ncell_tot = C.ncell;
+    P.nbrick_tot = C.nbrick;
+    P.b_lo = 0;
+    P.nb_launch = C.nbrick;
+    P.k_max = opt.k_max;
+    P.nchunk = opt.k_max / CHUNK;
+    P.block = opt.block;
+    P.stage_cap = opt.stage_cap;
+    P.nh_max = C.nh_max;
+    P.bcap_max = C.bcap_max;
+    P.ncb_max = C.ncb_max;
+    P.ntypes_max = C.ntypes_max;
+    P.any_chains = C.any_chains;
+    P.precision = opt.precision;
+    return P;
+}
+
+Launch restrict_to(const Launch &P, const RepDev &R)
+{
+    Launch Q = P;
+    Q.b_lo = R.b_off;
+    Q.nb_launch = R.nbrick;
+    return Q;
 }
 
 template <class T> T *at(void *base, size_t off) { return (T *)((char *)base + off); }
@@ -363,17 +441,186 @@ vbc_status hip_fail(vbc_handle h, hipError_t e, const char *where)
         if (_e != hipSuccess) return hip_fail(h, _e, where);     \
     } while (0)
 
+// Validate the capacity against the device's LDS, make the handle, carve the workspace
+// and clear it (synchronously on s).
+vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d_ws,
+                       size_t ws_bytes, hipStream_t s, vbc_handle *out)
+{
+    Launch P = launch_for(C, opt);
+    Offsets o = layout(C, opt.precision, P.nchunk, P.stage_cap);
+    if (!d_ws) return fail(VBC_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)d_ws) & 255) return fail(VBC_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < o.bytes)
+        return fail(VBC_ERR_CAPACITY, "workspace too small: need " + std::to_string(o.bytes) + " bytes");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    int lds_max = 0;
+    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
+    size_t need = std::max(std::max(lds_bytes_nlist(P), lds_bytes_count(P)),
+                           std::max(std::max(lds_bytes_embed(P), lds_bytes_force(P)),
+                                    lds_bytes_sort(P)));
+    if (need + 2048 > (size_t)lds_max)
+        return fail(VBC_ERR_CAPACITY, "staging needs " + std::to_string(need) +
+                                          " bytes of LDS per workgroup; the device allows " +
+                                          std::to_string(lds_max) + " (lower brick or stage_cap)");
+
+    vbc_handle h = new (std::nothrow) vbc_handle_s;
+    if (!h) return fail(VBC_ERR_ARG, "out of host memory");
+    h->P = P;
+    h->opt = opt;
+    h->pool = pool;
+    h->reps.assign(C.nrep, RepDev{});
+    for (auto &R : h->reps) std::memset(&R, 0, sizeof(R));
+    h->live.assign(C.nrep, 0);
+    h->has_state.assign(C.nrep, 0);
+    h->need_full.assign(C.nrep, 0);
+    h->fvalid.assign(C.nrep, 0);
+    h->up_pending.assign(C.nrep, 0);
+    h->a_slot.init(C.nslots);
+    h->a_brick.init(C.nbrick);
+    h->a_cell.init(C.ncell);
+    h->a_caller.init(C.ntot);
+    Buffers &B = h->B;
+    B.reps = at<RepDev>(d_ws, o.reps);
+    B.brick_rep = at<int32_t>(d_ws, o.brick_rep);
+    B.cell_rank = at<int32_t>(d_ws, o.cell_rank);
+    B.brick_rank0 = at<int32_t>(d_ws, o.brick_rank0);
+    B.cstart[0] = at<int32_t>(d_ws, o.cstart0);
+    B.cstart[1] = at<int32_t>(d_ws, o.cstart1);
+    B.ccnt[0] = at<int32_t>(d_ws, o.ccnt0);
+    B.ccnt[1] = at<int32_t>(d_ws, o.ccnt1);
+    B.bcnt[0] = at<int32_t>(d_ws, o.bcnt0);
+    B.bcnt[1] = at<int32_t>(d_ws, o.bcnt1);
+    B.bfill = at<int32_t>(d_ws, o.bfill);
+    B.x[0] = at<double>(d_ws, o.x0);
+    B.x[1] = at<double>(d_ws, o.x1);
+    B.v = at<double>(d_ws, o.v);
+    B.Fst = at<double>(d_ws, o.Fst);
+    B.xref = at<double>(d_ws, o.xref);
+    B.tag = at<int32_t>(d_ws, o.tag);
+    B.type = at<int32_t>(d_ws, o.type);
+    B.lcell = at<uint8_t>(d_ws, o.lcell);
+    B.xs = at<double>(d_ws, o.xs);
+    B.vs = at<double>(d_ws, o.vs);
+    B.tags = at<int32_t>(d_ws, o.tags);
+    B.types = at<int32_t>(d_ws, o.types);
+    B.lcells = at<uint8_t>(d_ws, o.lcells);
+    B.src = at<int32_t>(d_ws, o.src);
+    B.inv = at<int32_t>(d_ws, o.inv);
+    B.smap = at<int32_t>(d_ws, o.smap);
+    B.wmap = at<uint8_t>(d_ws, o.wmap);
+    B.stotal = at<int32_t>(d_ws, o.stotal);
+    B.nl = at<uint4>(d_ws, o.nl);
+    B.nn = at<uint16_t>(d_ws, o.nn);
+    B.nd = at<double>(d_ws, o.nd);
+    B.sA = at<void>(d_ws, o.sA);
+    B.win = at<uint8_t>(d_ws, o.win);
+    B.part = at<double>(d_ws, o.part);
+    B.flags = at<uint32_t>(d_ws, o.flags);
+    B.step = at<uint64_t>(d_ws, o.step);
+    B.stats = at<unsigned long long>(d_ws, o.stats);
+    B.bevals = at<unsigned long long>(d_ws, o.bevals);
+    B.bentries = at<uint32_t>(d_ws, o.bentries);
+    B.stamps = at<unsigned long long>(d_ws, o.stamps);
+    B.stamp_n = at<unsigned long long>(d_ws, o.stamp_n);
+
+    e = hipHostMalloc((void **)&h->up, sizeof(RepDev) * std::max(C.nrep, 1), hipHostMallocDefault);
+    if (e == hipSuccess) {
+        h->up_ev.assign(C.nrep, nullptr);
+        for (int r = 0; r < C.nrep && e == hipSuccess; ++r)
+            e = hipEventCreateWithFlags(&h->up_ev[r], hipEventDisableTiming);
+    }
+    // every brick starts free (owner -1: all bytes 0xFF), everything else at zero
+    if (e == hipSuccess) e = hipMemsetAsync(d_ws, 0, o.bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(B.brick_rep, 0xFF, sizeof(int32_t) * C.nbrick, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        vbc_status r = hip_fail(nullptr, e, "workspace set-up");
+        delete h;
+        return r;
+    }
+    *out = h;
+    return VBC_OK;
+}
+
+// Place a planned replica in a free slot: take its ranges, upload its descriptor and
+// write its tables (stream-ordered after all earlier work on s).
+vbc_status place(vbc_handle h, const RepPlan &rp, hipStream_t s, int32_t *rep_out)
+{
+    int r = -1;
+    for (int k = 0; k < h->P.nrep; ++k)
+        if (!h->live[k]) { r = k; break; }
+    if (r < 0) return hfail(h, VBC_ERR_CAPACITY, "no free replica slot");
+    RepDev R = rp.R;
+    int64_t p = h->a_slot.take(rp.slots);
+    int64_t b = p < 0 ? -1 : h->a_brick.take(R.nbrick);
+    int64_t c = b < 0 ? -1 : h->a_cell.take(R.ncell);
+    int64_t o = c < 0 ? -1 : h->a_caller.take(R.n);
+    if (o < 0) {
+        if (c >= 0) h->a_cell.give(c, R.ncell);
+        if (b >= 0) h->a_brick.give(b, R.nbrick);
+        if (p >= 0) h->a_slot.give(p, rp.slots);
+        const char *what = p < 0 ? "particle slots" : b < 0 ? "bricks" : c < 0 ? "cells" : "particles";
+        return hfail(h, VBC_ERR_CAPACITY, std::string("no contiguous range of ") + what + " left");
+    }
+    R.p_off = p;
+    R.b_off = (int32_t)b;
+    R.c_off = (int32_t)c;
+    R.o_off = o;
+    if (h->up_pending[r]) VBC_TRY(h, hipEventSynchronize(h->up_ev[r]), "upload wait");
+    h->up[r] = R;
+    VBC_TRY(h, hipMemcpyAsync(h->B.reps + r, h->up + r, sizeof(RepDev), hipMemcpyHostToDevice, s),
+            "descriptor upload");
+    VBC_TRY(h, hipEventRecord(h->up_ev[r], s), "upload event");
+    h->up_pending[r] = 1;
+    VBC_TRY(h, launch_admit(h->B, r, std::max<int64_t>(R.nbrick, R.ncell), s), "admit");
+    h->reps[r] = R;
+    h->live[r] = 1;
+    h->has_state[r] = 0;
+    h->need_full[r] = 0;
+    h->fvalid[r] = 0;
+    *rep_out = r;
+    return VBC_OK;
+}
+
+bool any_live(vbc_handle h)
+{
+    for (char l : h->live)
+        if (l) return true;
+    return false;
+}
+
+bool all_have_state(vbc_handle h)
+{
+    for (int r = 0; r < h->P.nrep; ++r)
+        if (h->live[r] && !h->has_state[r]) return false;
+    return true;
+}
+
 }  // namespace
 
-// The first build after vbc_set_state starts from caller-order input.
+#define VBC_NEED_STATE(h)                                                      \
+    do {                                                                       \
+        if (!any_live(h)) return hfail(h, VBC_ERR_STATE, "no live replica");   \
+        if (!all_have_state(h)) return hfail(h, VBC_ERR_STATE, "no state set"); \
+    } while (0)
+
+// Replicas whose state was set from caller-order input get a full build (bin, sort,
+// list) of their own bricks before anything reads their layout.
 static vbc_status ensure_layout(vbc_handle h, hipStream_t s)
 {
-    if (!h->need_full) return VBC_OK;
-    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_full_build(h->B, h->P, h->cur, s); }),
-            "full build");
-    VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD | FLAG_FULL, false, s), "flags");
-    h->need_full = false;
-    h->f_valid = false;
+    for (int r = 0; r < h->P.nrep; ++r) {
+        if (!h->live[r] || !h->need_full[r]) continue;
+        const RepDev &R = h->reps[r];
+        Launch Q = restrict_to(h->P, R);
+        VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_full_build(h->B, Q, h->cur, r, R.n, s); }),
+                "full build");
+        VBC_TRY(h, launch_flags(h->B, r, 1, VBC_FLAG_REBUILD | FLAG_FULL, false, s), "flags");
+        h->need_full[r] = 0;
+        h->fvalid[r] = 0;
+    }
     return VBC_OK;
 }
 
@@ -383,108 +630,364 @@ static vbc_status ensure_layout(vbc_handle h, hipStream_t s)
         if (_st != VBC_OK) return _st;            \
     } while (0)
 
-extern "C" {
-
-vbc_status vbc_workspace_size(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt,
-                              size_t *bytes)
+static StepArgs no_step()
 {
-    if (!bytes) return fail(VBC_ERR_ARG, "bytes is NULL");
-    Layout Lo;
-    vbc_status st = plan(reps, nrep, opt, Lo);
-    if (st != VBC_OK) return st;
-    *bytes = Lo.bytes;
+    StepArgs st;
+    std::memset(&st, 0, sizeof(st));
+    return st;
+}
+
+// count, embed and force of the current positions into Fst (and the optional outputs),
+// over the bricks that Q covers
+static vbc_status eval_forces(vbc_handle h, const Launch &Q, bool thermo, const StepArgs &st,
+                              double *d_F, double *d_e, hipStream_t s)
+{
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, Q, h->cur, s); }), "rebuild");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, Q, h->cur, nullptr, 0, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, Q, h->cur, s); }), "embed");
+    VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
+                return launch_force(h->B, Q, h->cur, MODE_EVAL, thermo, st, d_F, d_e, s);
+            }),
+            "force");
     return VBC_OK;
 }
 
-vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt,
+// Forces for the replicas that have none stored yet: all bricks at once when no live
+// replica has them, else replica by replica so that the others are left untouched.
+static vbc_status eval_missing(vbc_handle h, const StepArgs &st, hipStream_t s)
+{
+    int missing = 0, live = 0;
+    for (int r = 0; r < h->P.nrep; ++r)
+        if (h->live[r]) {
+            ++live;
+            if (!h->fvalid[r]) ++missing;
+        }
+    if (!missing) return VBC_OK;
+    if (missing == live) {
+        vbc_status st2 = eval_forces(h, h->P, false, st, nullptr, nullptr, s);
+        if (st2 != VBC_OK) return st2;
+    } else {
+        for (int r = 0; r < h->P.nrep; ++r) {
+            if (!h->live[r] || h->fvalid[r]) continue;
+            vbc_status st2 = eval_forces(h, restrict_to(h->P, h->reps[r]), false, st, nullptr, nullptr, s);
+            if (st2 != VBC_OK) return st2;
+        }
+    }
+    for (int r = 0; r < h->P.nrep; ++r)
+        if (h->live[r]) h->fvalid[r] = 1;
+    return VBC_OK;
+}
+
+// One step after the opening kick, from position buffer c: list rebuild when due, count,
+// dU/dn, force with the closing kick (MODE_MID: and the opening of the next step), and
+// the step's time stamp when those are on.
+static hipError_t launch_step(vbc_handle h, int c, const StepArgs &st, Mode mode, hipStream_t s)
+{
+    hipError_t e = timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, c, s); });
+    if (e == hipSuccess)
+        e = timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, c, nullptr, 1, s); });
+    if (e == hipSuccess) e = timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, c, s); });
+    if (e == hipSuccess)
+        e = timed(h, VBC_K_FORCE, s, [&] {
+            return launch_force(h->B, h->P, c, mode, false, st, nullptr, nullptr, s);
+        });
+    if (e == hipSuccess && h->stamps) e = launch_stamp(h->B, s);
+    return e;
+}
+
+static hipError_t launch_kick(vbc_handle h, int c, const StepArgs &st, hipStream_t s)
+{
+    return timed(h, VBC_K_KICK, s, [&] { return launch_kick_drift(h->B, h->P, c, st, s); });
+}
+
+static bool same_step_args(const StepArgs &a, const StepArgs &b)
+{
+    return a.kind == b.kind && a.dt == b.dt && a.hdt == b.hdt && a.c1 == b.c1 && a.c2s == b.c2s &&
+           a.seed == b.seed;
+}
+
+// Graph kinds: 0 = GRAPH_STEPS mid-call steps from buffer c; 1 = a whole call of nsteps
+// steps (opening kick, nsteps - 1 mid-call steps, closing step) from buffer c.  Captured
+// once per setting on a private stream and launched on the caller's stream; they hold
+// kernel nodes only, every data-dependent choice (rebuild or not, which bricks are live)
+// is taken on the GPU, so replicas may enter and leave between launches.
+static hipError_t get_graph(vbc_handle h, int kind, int nsteps, int c, const StepArgs &st,
+                            hipGraphExec_t *out)
+{
+    for (auto &g : h->graphs)
+        if (g.kind == kind && g.nsteps == nsteps && g.c == c && g.stamps == h->stamps &&
+            same_step_args(g.st, st)) {
+            *out = g.exec;
+            return hipSuccess;
+        }
+    hipError_t e = hipSuccess;
+    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    int cc = c;
+    if (kind == 0) {
+        for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k) {
+            le = launch_step(h, cc, st, MODE_MID, h->cap_stream);
+            cc ^= 1;
+        }
+    } else {
+        le = launch_kick(h, cc, st, h->cap_stream);
+        cc ^= 1;
+        for (int k = 1; k < nsteps && le == hipSuccess; ++k) {
+            le = launch_step(h, cc, st, MODE_MID, h->cap_stream);
+            cc ^= 1;
+        }
+        if (le == hipSuccess) le = launch_step(h, cc, st, MODE_LAST, h->cap_stream);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &g);
+    if (le != hipSuccess) e = le;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    if (h->graphs.size() >= GRAPH_CACHE) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back({kind, nsteps, c, h->stamps, st, ex});
+    *out = ex;
+    return hipSuccess;
+}
+
+extern "C" {
+
+vbc_status vbc_workspace_size(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in,
+                              size_t *bytes);
+
+// Capacity, options and plans of a fixed replica set (vbc_create).
+static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in,
+                           Caps &C, vbc_options &opt, std::vector<RepPlan> &plans)
+{
+    if (!reps || nrep < 1) return fail(VBC_ERR_ARG, "need at least one replica");
+    vbc_status st = check_options(opt_in, opt);
+    if (st != VBC_OK) return st;
+    plans.resize(nrep);
+    double rho_cell_max = 0.0, k_mean_max = 0.0, own_mean_max = 0.0;
+    C.nrep = nrep;
+    for (int r = 0; r < nrep; ++r) {
+        st = plan_replica(reps[r], opt.brick, plans[r]);
+        if (st != VBC_OK) {
+            g_err = "replica " + std::to_string(r) + ": " + g_err;
+            return st;
+        }
+        const RepPlan &p = plans[r];
+        C.ntot += p.R.n;
+        C.nslots += p.slots;
+        C.nbrick += p.R.nbrick;
+        C.ncell += p.R.ncell;
+        C.nh_max = std::max(C.nh_max, p.nh);
+        C.ncb_max = std::max(C.ncb_max, p.ncb);
+        C.bcap_max = std::max(C.bcap_max, (int)p.R.bcap);
+        C.ntypes_max = std::max(C.ntypes_max, (int)p.R.ntypes);
+        if (p.R.chain_len) C.any_chains = 1;
+        rho_cell_max = std::max(rho_cell_max, p.rho_cell);
+        own_mean_max = std::max(own_mean_max, p.own_mean);
+        k_mean_max = std::max(k_mean_max, p.k_mean);
+        if (C.nslots >= ((int64_t)1 << 31) - 1 || C.nbrick >= (1 << 30) || C.ncell >= (1 << 30))
+            return fail(VBC_ERR_ARG, "more than 2^31 slots in total");
+    }
+    if (!opt.block) opt.block = std::max(128, std::min(512, round_up((int)std::ceil(own_mean_max), 64)));
+    opt.k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : k_max_for(k_mean_max);
+    if (!opt.stage_cap) opt.stage_cap = stage_cap_for(rho_cell_max, C.nh_max);
+    return VBC_OK;
+}
+
+vbc_status vbc_workspace_size(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in,
+                              size_t *bytes)
+{
+    if (!bytes) return fail(VBC_ERR_ARG, "bytes is NULL");
+    Caps C;
+    vbc_options opt;
+    std::vector<RepPlan> plans;
+    vbc_status st = plan_set(reps, nrep, opt_in, C, opt, plans);
+    if (st != VBC_OK) return st;
+    *bytes = layout(C, opt.precision, opt.k_max / CHUNK, opt.stage_cap).bytes;
+    return VBC_OK;
+}
+
+vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_options *opt_in,
                       void *d_ws, size_t ws_bytes, hipStream_t s, vbc_handle *out)
 {
     if (!out) return fail(VBC_ERR_ARG, "out is NULL");
     *out = nullptr;
-    Layout Lo;
-    vbc_status st = plan(reps, nrep, opt, Lo);
+    Caps C;
+    vbc_options opt;
+    std::vector<RepPlan> plans;
+    vbc_status st = plan_set(reps, nrep, opt_in, C, opt, plans);
     if (st != VBC_OK) return st;
-    if (!d_ws) return fail(VBC_ERR_ARG, "workspace is NULL");
-    if (((uintptr_t)d_ws) & 255) return fail(VBC_ERR_ARG, "workspace must be 256-byte aligned");
-    if (ws_bytes < Lo.bytes)
-        return fail(VBC_ERR_CAPACITY, "workspace too small: need " + std::to_string(Lo.bytes) + " bytes");
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
-    int lds_max = 0;
-    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
-    size_t need = std::max(std::max(lds_bytes_nlist(Lo.P), lds_bytes_count(Lo.P)),
-                           std::max(std::max(lds_bytes_embed(Lo.P), lds_bytes_force(Lo.P)),
-                                    lds_bytes_sort(Lo.P)));
-    if (need + 2048 > (size_t)lds_max)
-        return fail(VBC_ERR_CAPACITY, "staging needs " + std::to_string(need) +
-                                          " bytes of LDS per workgroup; the device allows " +
-                                          std::to_string(lds_max) + " (lower brick or stage_cap)");
-
-    vbc_handle h = new (std::nothrow) vbc_handle_s;
-    if (!h) return fail(VBC_ERR_ARG, "out of host memory");
-    h->P = Lo.P;
-    h->reps = Lo.reps;
-    h->opt = Lo.opt;
-    Buffers &B = h->B;
-    B.reps = at<RepDev>(d_ws, Lo.o_reps);
-    B.cell_rank = at<int32_t>(d_ws, Lo.o_cell_rank);
-    B.brick_rank0 = at<int32_t>(d_ws, Lo.o_brick_rank0);
-    B.cstart[0] = at<int32_t>(d_ws, Lo.o_cstart0);
-    B.cstart[1] = at<int32_t>(d_ws, Lo.o_cstart1);
-    B.ccnt[0] = at<int32_t>(d_ws, Lo.o_ccnt0);
-    B.ccnt[1] = at<int32_t>(d_ws, Lo.o_ccnt1);
-    B.bcnt[0] = at<int32_t>(d_ws, Lo.o_bcnt0);
-    B.bcnt[1] = at<int32_t>(d_ws, Lo.o_bcnt1);
-    B.bfill = at<int32_t>(d_ws, Lo.o_bfill);
-    B.x[0] = at<double>(d_ws, Lo.o_x0);
-    B.x[1] = at<double>(d_ws, Lo.o_x1);
-    B.v = at<double>(d_ws, Lo.o_v);
-    B.Fst = at<double>(d_ws, Lo.o_Fst);
-    B.xref = at<double>(d_ws, Lo.o_xref);
-    B.tag = at<int32_t>(d_ws, Lo.o_tag);
-    B.type = at<int32_t>(d_ws, Lo.o_type);
-    B.lcell = at<uint8_t>(d_ws, Lo.o_lcell);
-    B.xs = at<double>(d_ws, Lo.o_xs);
-    B.vs = at<double>(d_ws, Lo.o_vs);
-    B.tags = at<int32_t>(d_ws, Lo.o_tags);
-    B.types = at<int32_t>(d_ws, Lo.o_types);
-    B.lcells = at<uint8_t>(d_ws, Lo.o_lcells);
-    B.src = at<int32_t>(d_ws, Lo.o_src);
-    B.inv = at<int32_t>(d_ws, Lo.o_inv);
-    B.smap = at<int32_t>(d_ws, Lo.o_smap);
-    B.wmap = at<uint8_t>(d_ws, Lo.o_wmap);
-    B.stotal = at<int32_t>(d_ws, Lo.o_stotal);
-    B.nl = at<uint4>(d_ws, Lo.o_nl);
-    B.nn = at<uint16_t>(d_ws, Lo.o_nn);
-    B.nd = at<double>(d_ws, Lo.o_nd);
-    B.sA = at<void>(d_ws, Lo.o_sA);
-    B.win = at<uint8_t>(d_ws, Lo.o_win);
-    B.part = at<double>(d_ws, Lo.o_part);
-    B.flags = at<uint32_t>(d_ws, Lo.o_flags);
-    B.step = at<uint64_t>(d_ws, Lo.o_step);
-    B.stats = at<unsigned long long>(d_ws, Lo.o_stats);
-    B.bevals = at<unsigned long long>(d_ws, Lo.o_bevals);
-    B.bentries = at<uint32_t>(d_ws, Lo.o_bentries);
-
-    // static tables; everything else starts at zero (no particle in any brick)
-    e = hipMemsetAsync(d_ws, 0, Lo.bytes, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B.reps, Lo.reps.data(), sizeof(RepDev) * nrep, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B.cell_rank, Lo.cell_rank.data(), sizeof(int32_t) * Lo.cell_rank.size(),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B.brick_rank0, Lo.brick_rank0.data(),
-                           sizeof(int32_t) * Lo.brick_rank0.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    vbc_handle h = nullptr;
+    st = make_handle(C, opt, false, d_ws, ws_bytes, s, &h);
+    if (st != VBC_OK) return st;
+    // first fit on empty ranges: replica r lands at the prefix sums of the ones before it
+    for (int r = 0; r < nrep; ++r) {
+        int32_t got = -1;
+        st = place(h, plans[r], s, &got);
+        if (st != VBC_OK || got != r) {
+            if (st == VBC_OK) st = hfail(h, VBC_ERR_CAPACITY, "replica placement");
+            g_err = h->err;
+            delete h;
+            return st;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        vbc_status r = hip_fail(h, e, "vbc_create upload");
+        vbc_status r = hip_fail(nullptr, e, "vbc_create upload");
         delete h;
         return r;
     }
     *out = h;
+    return VBC_OK;
+}
+
+static vbc_status check_caps(const vbc_pool_caps *caps, const vbc_options &opt, Caps &C)
+{
+    if (!caps) return fail(VBC_ERR_ARG, "caps is NULL");
+    if (caps->max_replicas < 1 || caps->max_replicas > (1 << 20))
+        return fail(VBC_ERR_ARG, "max_replicas must be 1..2^20");
+    if (caps->max_types < 1 || caps->max_types > MAXT) return fail(VBC_ERR_ARG, "max_types must be 1..4");
+    if (caps->max_particles < 1 || caps->max_slots < caps->max_particles)
+        return fail(VBC_ERR_ARG, "need 1 <= max_particles <= max_slots");
+    if (caps->max_slots >= ((int64_t)1 << 31) - 1) return fail(VBC_ERR_ARG, "max_slots must be < 2^31");
+    if (caps->max_bricks < 1 || caps->max_cells < caps->max_bricks)
+        return fail(VBC_ERR_ARG, "need 1 <= max_bricks <= max_cells");
+    if (caps->max_bcap < 64) return fail(VBC_ERR_ARG, "max_bcap must be >= 64");
+    if (opt.k_max <= 0 || opt.stage_cap <= 0)
+        return fail(VBC_ERR_ARG, "a pool needs k_max and stage_cap set explicitly");
+    C.nrep = caps->max_replicas;
+    C.ntypes_max = caps->max_types;
+    C.any_chains = caps->chains ? 1 : 0;
+    C.bcap_max = caps->max_bcap;
+    C.nh_max = (opt.brick + 2) * (opt.brick + 2) * (opt.brick + 2);
+    C.ncb_max = opt.brick * opt.brick * opt.brick;
+    C.ntot = caps->max_particles;
+    C.nslots = caps->max_slots;
+    C.nbrick = caps->max_bricks;
+    C.ncell = caps->max_cells;
+    return VBC_OK;
+}
+
+static vbc_status pool_options(const vbc_options *opt_in, vbc_options &opt)
+{
+    vbc_status st = check_options(opt_in, opt);
+    if (st != VBC_OK) return st;
+    if (!opt.block) opt.block = 256;
+    opt.k_max = round_up(opt.k_max, CHUNK);
+    return VBC_OK;
+}
+
+vbc_status vbc_pool_workspace_size(const vbc_pool_caps *caps, const vbc_options *opt_in, size_t *bytes)
+{
+    if (!bytes) return fail(VBC_ERR_ARG, "bytes is NULL");
+    vbc_options opt;
+    vbc_status st = pool_options(opt_in, opt);
+    if (st != VBC_OK) return st;
+    Caps C;
+    st = check_caps(caps, opt, C);
+    if (st != VBC_OK) return st;
+    *bytes = layout(C, opt.precision, opt.k_max / CHUNK, opt.stage_cap).bytes;
+    return VBC_OK;
+}
+
+vbc_status vbc_pool_create(const vbc_pool_caps *caps, const vbc_options *opt_in, void *d_ws,
+                           size_t ws_bytes, hipStream_t s, vbc_handle *out)
+{
+    if (!out) return fail(VBC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    vbc_options opt;
+    vbc_status st = pool_options(opt_in, opt);
+    if (st != VBC_OK) return st;
+    Caps C;
+    st = check_caps(caps, opt, C);
+    if (st != VBC_OK) return st;
+    return make_handle(C, opt, true, d_ws, ws_bytes, s, out);
+}
+
+vbc_status vbc_replica_footprint(const vbc_replica_desc *d, const vbc_options *opt_in, vbc_footprint *out)
+{
+    if (!d || !out) return fail(VBC_ERR_ARG, "NULL argument");
+    vbc_options opt;
+    vbc_status st = check_options(opt_in, opt);
+    if (st != VBC_OK) return st;
+    RepPlan rp;
+    st = plan_replica(*d, opt.brick, rp);
+    if (st != VBC_OK) return st;
+    int k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : rp.k_max_auto;
+    int stage_cap = opt.stage_cap ? opt.stage_cap : rp.stage_cap_auto;
+    out->slots = rp.slots;
+    out->bricks = rp.R.nbrick;
+    out->cells = rp.R.ncell;
+    out->bcap = rp.R.bcap;
+    out->k_max = rp.k_max_auto;
+    out->stage_cap = rp.stage_cap_auto;
+    out->brick = std::max(rp.R.bd[0], std::max(rp.R.bd[1], rp.R.bd[2]));
+    out->bytes = footprint_bytes(rp, opt.precision, k_max / CHUNK, stage_cap);
+    return VBC_OK;
+}
+
+vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x, const double *d_v,
+                     const int32_t *d_type, uint64_t step0, hipStream_t s, int32_t *rep_out)
+{
+    if (!h || !d || !d_x || !rep_out) return fail(VBC_ERR_ARG, "NULL argument");
+    *rep_out = -1;
+    RepPlan rp;
+    vbc_status st = plan_replica(*d, h->opt.brick, rp);
+    if (st != VBC_OK) return hfail(h, st, g_err);
+    const RepDev &R = rp.R;
+    if (R.ntypes > h->P.ntypes_max) return hfail(h, VBC_ERR_CAPACITY, "more particle types than the pool allows");
+    if (R.chain_len && !h->P.any_chains) return hfail(h, VBC_ERR_CAPACITY, "the pool was made without chains");
+    if (R.bcap > h->P.bcap_max)
+        return hfail(h, VBC_ERR_CAPACITY, "replica needs " + std::to_string(R.bcap) +
+                                              " slots per brick; the pool has " + std::to_string(h->P.bcap_max));
+    if (rp.nh > h->P.nh_max || rp.ncb > h->P.ncb_max)
+        return hfail(h, VBC_ERR_CAPACITY, "brick larger than the pool's");
+    if (h->pool && (rp.k_max_auto > h->P.k_max || rp.stage_cap_auto > h->P.stage_cap))
+        return hfail(h, VBC_ERR_CAPACITY, "replica too dense for the pool: needs k_max " +
+                                              std::to_string(rp.k_max_auto) + ", stage_cap " +
+                                              std::to_string(rp.stage_cap_auto));
+    int32_t r = -1;
+    st = place(h, rp, s, &r);
+    if (st != VBC_OK) return st;
+    const RepDev &Rp = h->reps[r];
+    VBC_TRY(h, launch_set_state(h->B, h->P, h->cur, r, Rp.n, d_x, d_v, d_type, 0, Rp.n, step0, s),
+            "set_state");
+    h->has_state[r] = 1;
+    h->need_full[r] = 1;
+    *rep_out = r;
+    return VBC_OK;
+}
+
+vbc_status vbc_retire(vbc_handle h, int32_t rep, hipStream_t s)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    if (rep < 0 || rep >= h->P.nrep || !h->live[rep]) return hfail(h, VBC_ERR_ARG, "no such live replica");
+    RepDev &R = h->reps[rep];
+    VBC_TRY(h, launch_retire(h->B, rep, R.b_off, R.nbrick, s), "retire");
+    h->a_slot.give(R.p_off, (int64_t)R.nbrick * R.bcap);
+    h->a_brick.give(R.b_off, R.nbrick);
+    h->a_cell.give(R.c_off, R.ncell);
+    h->a_caller.give(R.o_off, R.n);
+    std::memset(&R, 0, sizeof(R));
+    h->live[rep] = 0;
+    h->has_state[rep] = 0;
+    h->need_full[rep] = 0;
+    h->fvalid[rep] = 0;
+    return VBC_OK;
+}
+
+vbc_status vbc_replica_info(vbc_handle h, int32_t rep, int64_t *n, int64_t *caller_offset)
+{
+    if (!h || !n || !caller_offset) return fail(VBC_ERR_ARG, "NULL argument");
+    if (rep < 0 || rep >= h->P.nrep) return hfail(h, VBC_ERR_ARG, "replica index out of range");
+    *n = h->live[rep] ? h->reps[rep].n : 0;
+    *caller_offset = h->live[rep] ? h->reps[rep].o_off : 0;
     return VBC_OK;
 }
 
@@ -511,167 +1014,85 @@ vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const dou
                          const int32_t *d_type, uint64_t step0, hipStream_t s)
 {
     if (!h || !d_x) return fail(VBC_ERR_ARG, "NULL argument");
-    if (rep >= h->P.nrep) {
-        h->err = "replica index out of range";
-        return VBC_ERR_ARG;
+    if (rep >= h->P.nrep || (rep >= 0 && !h->live[rep])) return hfail(h, VBC_ERR_ARG, "no such live replica");
+    for (int r = 0; r < h->P.nrep; ++r) {
+        if (!h->live[r] || (rep >= 0 && r != rep)) continue;
+        const RepDev &R = h->reps[r];
+        int64_t off = rep < 0 ? R.o_off : 0, stride = rep < 0 ? h->P.ntot : R.n;
+        VBC_TRY(h, launch_set_state(h->B, h->P, h->cur, r, R.n, d_x, d_v, d_type, off, stride, step0, s),
+                "set_state");
+        h->has_state[r] = 1;
+        h->need_full[r] = 1;
+        h->fvalid[r] = 0;
     }
-    // a pending full build of other replicas must not see this one half-written
-    int64_t n = rep < 0 ? h->P.ntot : h->reps[rep].n;
-    int64_t off = rep < 0 ? 0 : h->reps[rep].o_off;
-    VBC_TRY(h, launch_set_state(h->B, h->P, h->cur, d_x, d_v, d_type, step0, s, n, off), "set_state");
-    h->f_valid = false;
-    h->have_state = true;
-    h->need_full = true;
     return VBC_OK;
 }
 
 vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    if (rep >= h->P.nrep) {
-        h->err = "replica index out of range";
-        return VBC_ERR_ARG;
-    }
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    if (rep >= h->P.nrep || (rep >= 0 && !h->live[rep])) return hfail(h, VBC_ERR_ARG, "no such live replica");
+    if (rep >= 0 ? !h->has_state[rep] : !all_have_state(h)) return hfail(h, VBC_ERR_STATE, "no state set");
     VBC_LAYOUT(h, s);
-    int lo = rep < 0 ? 0 : rep, hi = rep < 0 ? h->P.nrep - 1 : rep;
-    int64_t slot_lo = h->reps[lo].p_off;
-    int64_t slot_hi = h->reps[hi].p_off + (int64_t)h->reps[hi].nbrick * h->reps[hi].bcap;
-    int64_t out_off = h->reps[lo].o_off;
-    int64_t out_stride = rep < 0 ? h->P.ntot : h->reps[rep].n;
-    VBC_TRY(h, launch_get_state(h->B, h->P, h->cur, slot_lo, slot_hi - slot_lo, out_off, out_stride,
-                                d_x, d_v, s),
-            "get_state");
+    for (int r = 0; r < h->P.nrep; ++r) {
+        if (!h->live[r] || (rep >= 0 && r != rep)) continue;
+        const RepDev &R = h->reps[r];
+        int64_t off = rep < 0 ? R.o_off : 0, stride = rep < 0 ? h->P.ntot : R.n;
+        VBC_TRY(h, launch_get_state(h->B, h->P, h->cur, r, (int64_t)R.nbrick * R.bcap, off, stride, d_x, d_v, s),
+                "get_state");
+    }
     return VBC_OK;
 }
 
 vbc_status vbc_build_nlist(vbc_handle h, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
-    if (h->need_full) {
-        VBC_LAYOUT(h, s);
-        return VBC_OK;
-    }
-    VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD, true, s), "flags");
+    VBC_NEED_STATE(h);
+    bool full = false;
+    for (int r = 0; r < h->P.nrep; ++r) full = full || (h->live[r] && h->need_full[r]);
+    VBC_LAYOUT(h, s);
+    if (full) return VBC_OK;
+    VBC_TRY(h, launch_flags(h->B, 0, h->P.nrep, VBC_FLAG_REBUILD, true, s), "flags");
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, launch_flags(h->B, h->P, VBC_FLAG_REBUILD, false, s), "flags");
-    h->f_valid = false;
+    VBC_TRY(h, launch_flags(h->B, 0, h->P.nrep, VBC_FLAG_REBUILD, false, s), "flags");
+    for (int r = 0; r < h->P.nrep; ++r) h->fvalid[r] = 0;
     return VBC_OK;
 }
 
 vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
     VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, 0, s); }), "count");
     return VBC_OK;
 }
 
-static StepArgs no_step()
-{
-    StepArgs st;
-    std::memset(&st, 0, sizeof(st));
-    return st;
-}
-
-// count, embed and force of the current positions into Fst (and the optional outputs)
-static vbc_status eval_forces(vbc_handle h, bool thermo, const StepArgs &st, double *d_F, double *d_e,
-                              hipStream_t s)
-{
-    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 0, s); }), "count");
-    VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
-    VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
-                return launch_force(h->B, h->P, h->cur, MODE_EVAL, thermo, st, d_F, d_e, s);
-            }),
-            "force");
-    return VBC_OK;
-}
-
 vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipStream_t s)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
     bool thermo = d_e || d_UW;
-    vbc_status st = eval_forces(h, thermo, no_step(), d_F, d_e, s);
+    vbc_status st = eval_forces(h, h->P, thermo, no_step(), d_F, d_e, s);
     if (st != VBC_OK) return st;
     if (d_UW)
         VBC_TRY(h, timed(h, VBC_K_REDUCE, s, [&] { return launch_reduce(h->B, h->P, d_UW, s); }),
                 "reduce");
-    h->f_valid = true;
+    for (int r = 0; r < h->P.nrep; ++r) h->fvalid[r] = h->live[r];
     return VBC_OK;
-}
-
-// One mid-call step (list rebuild when due, count, dU/dn, force with the closing kick of
-// this step and the opening of the next) from position buffer c, on stream s.
-static hipError_t launch_mid_step(vbc_handle h, int c, const StepArgs &st, hipStream_t s)
-{
-    hipError_t e = launch_rebuild(h->B, h->P, c, s);
-    if (e == hipSuccess) e = launch_count(h->B, h->P, c, nullptr, 1, s);
-    if (e == hipSuccess) e = launch_embed(h->B, h->P, c, s);
-    if (e == hipSuccess) e = launch_force(h->B, h->P, c, MODE_MID, false, st, nullptr, nullptr, s);
-    return e;
-}
-
-static bool same_step_args(const StepArgs &a, const StepArgs &b)
-{
-    return a.kind == b.kind && a.dt == b.dt && a.hdt == b.hdt && a.c1 == b.c1 && a.c2s == b.c2s &&
-           a.seed == b.seed;
-}
-
-// Graph of GRAPH_STEPS mid-call steps starting from buffer c, captured once per integrator
-// setting on a private stream and launched on the caller's stream.  It holds kernel nodes
-// only; every data-dependent choice (rebuild or not) is taken on the GPU.
-static hipError_t step_graph(vbc_handle h, int c, const StepArgs &st, hipGraphExec_t *out)
-{
-    if (h->gexec[c] && same_step_args(h->gst[c], st)) {
-        *out = h->gexec[c];
-        return hipSuccess;
-    }
-    if (h->gexec[c]) {
-        (void)hipGraphExecDestroy(h->gexec[c]);
-        h->gexec[c] = nullptr;
-    }
-    hipError_t e = hipSuccess;
-    if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    int cc = c;
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k) {
-        le = launch_mid_step(h, cc, st, h->cap_stream);
-        cc ^= 1;
-    }
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(h->cap_stream, &g);
-    if (le != hipSuccess) e = le;
-    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[c], g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->gexec[c] = nullptr;
-        return e;
-    }
-    h->gst[c] = st;
-    *out = h->gexec[c];
-    return hipSuccess;
 }
 
 vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s)
 {
     if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
-    if (nsteps < 0) { h->err = "nsteps must be >= 0"; return VBC_ERR_ARG; }
-    if (it->kind != VBC_NVE && it->kind != VBC_LANGEVIN) { h->err = "bad integrator kind"; return VBC_ERR_ARG; }
-    if (!(it->dt > 0.0) || !std::isfinite(it->dt)) { h->err = "dt must be > 0"; return VBC_ERR_ARG; }
-    if (it->kind == VBC_LANGEVIN && (!(it->gamma >= 0.0) || !(it->kT >= 0.0))) {
-        h->err = "gamma and kT must be >= 0";
-        return VBC_ERR_ARG;
-    }
+    VBC_NEED_STATE(h);
+    if (nsteps < 0) return hfail(h, VBC_ERR_ARG, "nsteps must be >= 0");
+    if (it->kind != VBC_NVE && it->kind != VBC_LANGEVIN) return hfail(h, VBC_ERR_ARG, "bad integrator kind");
+    if (!(it->dt > 0.0) || !std::isfinite(it->dt)) return hfail(h, VBC_ERR_ARG, "dt must be > 0");
+    if (it->kind == VBC_LANGEVIN && (!(it->gamma >= 0.0) || !(it->kT >= 0.0)))
+        return hfail(h, VBC_ERR_ARG, "gamma and kT must be >= 0");
     if (nsteps == 0) return VBC_OK;
     VBC_LAYOUT(h, s);
     StepArgs st = no_step();
@@ -682,40 +1103,34 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
     st.c1 = std::exp(-it->gamma * it->dt);
     st.c2s = std::sqrt(1.0 - st.c1 * st.c1) * std::sqrt(it->kT);
     st.seed = it->seed;
-    if (!h->f_valid) {
-        vbc_status r = eval_forces(h, false, st, nullptr, nullptr, s);
-        if (r != VBC_OK) return r;
+    vbc_status r = eval_missing(h, st, s);
+    if (r != VBC_OK) return r;
+    const bool graphs = h->use_graphs && !h->prof;
+    if (graphs && nsteps <= CALL_GRAPH_MAX) {
+        // the whole call as one graph launch
+        hipGraphExec_t ge = nullptr;
+        VBC_TRY(h, get_graph(h, 1, nsteps, h->cur, st, &ge), "call graph");
+        VBC_TRY(h, hipGraphLaunch(ge, s), "graph launch");
+        h->cur ^= nsteps & 1;
+        return VBC_OK;
     }
     // opening half-kick and drift of the first step, from the stored forces
-    VBC_TRY(h, timed(h, VBC_K_KICK, s, [&] { return launch_kick_drift(h->B, h->P, h->cur, st, s); }), "kick");
+    VBC_TRY(h, launch_kick(h, h->cur, st, s), "kick");
     h->cur ^= 1;
     // nsteps - 1 mid-call steps: whole graphs, then single steps; kernel timing needs the
     // individual launches, so it bypasses the graphs
     int mid = nsteps - 1;
-    if (h->use_graphs && !h->prof && mid >= GRAPH_STEPS) {
+    if (graphs && mid >= GRAPH_STEPS) {
         hipGraphExec_t ge = nullptr;
-        VBC_TRY(h, step_graph(h, h->cur, st, &ge), "step graph");
+        VBC_TRY(h, get_graph(h, 0, GRAPH_STEPS, h->cur, st, &ge), "step graph");
         for (; mid >= GRAPH_STEPS; mid -= GRAPH_STEPS) VBC_TRY(h, hipGraphLaunch(ge, s), "graph launch");
     }
     for (; mid > 0; --mid) {
-        VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-        VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 1, s); }), "count");
-        VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
-        VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
-                    return launch_force(h->B, h->P, h->cur, MODE_MID, false, st, nullptr, nullptr, s);
-                }),
-                "force");
+        VBC_TRY(h, launch_step(h, h->cur, st, MODE_MID, s), "step");
         h->cur ^= 1;
     }
     // last step: closing half-kick only; its forces are kept for the next call
-    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, nullptr, 1, s); }), "count");
-    VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, h->cur, s); }), "embed");
-    VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
-                return launch_force(h->B, h->P, h->cur, MODE_LAST, false, st, nullptr, nullptr, s);
-            }),
-            "force");
-    h->f_valid = true;
+    VBC_TRY(h, launch_step(h, h->cur, st, MODE_LAST, s), "step");
     return VBC_OK;
 }
 
@@ -726,6 +1141,8 @@ vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica)
     std::vector<uint32_t> f(h->P.nrep);
     VBC_TRY(h, hipMemcpy(f.data(), h->B.flags, sizeof(uint32_t) * h->P.nrep, hipMemcpyDeviceToHost),
             "flags readback");
+    for (int r = 0; r < h->P.nrep; ++r)
+        if (!h->live[r]) f[r] = 0;
     if (flags_per_replica)
         for (int r = 0; r < h->P.nrep; ++r) flags_per_replica[r] = f[r] & 0xFFu;
     vbc_status st = VBC_OK;
@@ -747,7 +1164,7 @@ vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica)
         }
     }
     uint32_t errs = VBC_FLAG_NONFINITE | VBC_FLAG_NLIST_OVERFLOW | VBC_FLAG_STAGE_OVERFLOW | VBC_FLAG_LOST;
-    VBC_TRY(h, launch_flags(h->B, h->P, errs, false, s), "flags");
+    VBC_TRY(h, launch_flags(h->B, 0, h->P.nrep, errs, false, s), "flags");
     VBC_TRY(h, hipStreamSynchronize(s), "sync");
     return st;
 }
@@ -756,10 +1173,10 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
                          hipStream_t s)
 {
     if (!h || !d_count || (cap > 0 && !d_pairs)) return fail(VBC_ERR_ARG, "NULL argument");
-    if (rep < 0 || rep >= h->P.nrep) { h->err = "replica index out of range"; return VBC_ERR_ARG; }
-    if (!h->have_state) { h->err = "no state set"; return VBC_ERR_STATE; }
+    if (rep < 0 || rep >= h->P.nrep || !h->live[rep]) return hfail(h, VBC_ERR_ARG, "no such live replica");
+    if (!h->has_state[rep]) return hfail(h, VBC_ERR_STATE, "no state set");
     VBC_LAYOUT(h, s);
-    VBC_TRY(h, launch_rebuild(h->B, h->P, h->cur, s), "rebuild");
+    VBC_TRY(h, launch_rebuild(h->B, restrict_to(h->P, h->reps[rep]), h->cur, s), "rebuild");
     VBC_TRY(h, launch_export_nlist(h->B, h->P, rep, h->reps[rep].nbrick, d_pairs, cap, d_count, s),
             "export");
     return VBC_OK;
@@ -783,14 +1200,15 @@ vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out)
     for (int r = 0; r < h->P.nrep; ++r) {
         const RepDev &R = h->reps[r];
         unsigned long long pe = 0, le = 0;
-        for (int b = 0; b < R.nbrick; ++b) {
-            pe += ev[R.b_off + b];
-            le += en[R.b_off + b];
-        }
-        out[r].builds = v[4 * r];
+        if (h->live[r])
+            for (int b = 0; b < R.nbrick; ++b) {
+                pe += ev[R.b_off + b];
+                le += en[R.b_off + b];
+            }
+        out[r].builds = h->live[r] ? v[4 * r] : 0;
         out[r].list_entries = le;
         out[r].pair_evals = pe;
-        out[r].evals = v[4 * r + 3];
+        out[r].evals = h->live[r] ? v[4 * r + 3] : 0;
     }
     return VBC_OK;
 }
@@ -798,7 +1216,7 @@ vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out)
 vbc_status vbc_profile(vbc_handle h, int32_t enable, int32_t max_launches)
 {
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
-    if (enable && max_launches <= 0) { h->err = "max_launches must be > 0"; return VBC_ERR_ARG; }
+    if (enable && max_launches <= 0) return hfail(h, VBC_ERR_ARG, "max_launches must be > 0");
     h->prof = enable != 0;
     for (int k = 0; k < VBC_NK; ++k) h->prof_n[k] = 0;
     if (!h->prof) return VBC_OK;
@@ -828,6 +1246,40 @@ vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms, int64_t *la
         launches[k] = h->prof_n[k];
         h->prof_n[k] = 0;
     }
+    return VBC_OK;
+}
+
+vbc_status vbc_stamps(vbc_handle h, int32_t enable, hipStream_t s)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    h->stamps = enable != 0;
+    VBC_TRY(h, hipMemsetAsync(h->B.stamp_n, 0, sizeof(unsigned long long), s), "stamp reset");
+    return VBC_OK;
+}
+
+vbc_status vbc_stamps_read(vbc_handle h, hipStream_t s, uint64_t *out, int64_t cap, int64_t *n,
+                           double *hz)
+{
+    if (!h || !n || !hz || (cap > 0 && !out)) return fail(VBC_ERR_ARG, "NULL argument");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
+    unsigned long long total = 0;
+    VBC_TRY(h, hipMemcpy(&total, h->B.stamp_n, sizeof(total), hipMemcpyDeviceToHost), "stamp count");
+    int64_t keep = std::min<int64_t>((int64_t)total, std::min<int64_t>(STAMP_CAP, std::max<int64_t>(cap, 0)));
+    std::vector<unsigned long long> ring(STAMP_CAP);
+    if (keep > 0) {
+        VBC_TRY(h, hipMemcpy(ring.data(), h->B.stamps, sizeof(unsigned long long) * STAMP_CAP,
+                             hipMemcpyDeviceToHost),
+                "stamp readback");
+        for (int64_t k = 0; k < keep; ++k)
+            out[k] = ring[(total - keep + (uint64_t)k) & (STAMP_CAP - 1)];
+    }
+    *n = keep;
+    int dev = 0, khz = 0;
+    VBC_TRY(h, hipGetDevice(&dev), "hipGetDevice");
+    VBC_TRY(h, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "clock rate");
+    *hz = 1e3 * (double)khz;
+    VBC_TRY(h, hipMemsetAsync(h->B.stamp_n, 0, sizeof(unsigned long long), s), "stamp reset");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
     return VBC_OK;
 }
 

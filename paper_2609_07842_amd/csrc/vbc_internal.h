@@ -1,7 +1,10 @@
 // vbc_internal.h -- device-side data layout of libvbc (gfx950).
 //
 // Space is cut into cells of edge >= the list radius, and cells into "bricks" of up to
-// bd^3 cells; one workgroup owns one brick.  Every brick has a fixed number of particle
+// bd^3 cells; one workgroup owns one brick.  The workspace is a pool of fixed capacity
+// (replica descriptors, bricks, cells, particle slots, caller-order indices); a replica
+// takes a contiguous range of each, and a table gives the owner of every brick (-1 for a
+// free one), so replicas can enter and leave without changing any launch shape.  Every brick has a fixed number of particle
 // slots (bcap), so a replica's particles live in nbrick * bcap slots without any global
 // prefix sum: brick b of replica r owns slots [p_off + b * bcap, p_off + b * bcap + bcnt[b]),
 // sorted by cell (cells in x-fastest order inside the brick) and by tag inside a cell.
@@ -56,6 +59,7 @@ struct RepDev {
     double rlist2;         // list radius squared (FP64, exact comparison)
     double disp2;          // squared displacement that triggers a rebuild ((skin/2)^2)
     double k_bond, r0_bond;
+    uint64_t seed;         // added to the integrator's seed: this replica's noise key
     PairDev pair[MAXT * MAXT];
 };
 
@@ -63,6 +67,7 @@ struct RepDev {
 // sorted layout into "next" and the list kernel copies each brick into "live".
 struct Buffers {
     RepDev *reps;            // [nrep]
+    int32_t *brick_rep;      // [nbrick_tot] replica owning each brick, -1 = free
     int32_t *cell_rank;      // [sum ncell]  cell linear index -> brick-major rank (static)
     int32_t *brick_rank0;    // [nbrick_tot] rank of a brick's first cell (static)
     int32_t *cstart[2];      // [sum ncell] first slot of each cell (by rank)
@@ -96,14 +101,19 @@ struct Buffers {
     unsigned long long *stats;  // [nrep][4] builds, -, -, count passes
     unsigned long long *bevals; // [nbrick_tot] pair evaluations of each brick, summed over passes
     uint32_t *bentries;         // [nbrick_tot] list entries of each brick at the last build
+    unsigned long long *stamps; // [STAMP_CAP] device clock at the end of each stamped step
+    unsigned long long *stamp_n; // [1] stamps written so far
 };
 
+constexpr int STAMP_CAP = 1 << 16;  // power of two
+
 struct Launch {
-    int nrep;
+    int nrep;                // replica slots
     int64_t ntot;            // particles
     int64_t nslots;          // slots (sum nbrick * bcap)
     int32_t ncell_tot;
     int32_t nbrick_tot;
+    int32_t b_lo, nb_launch; // bricks one launch covers: [b_lo, b_lo + nb_launch)
     int32_t k_max;           // multiple of CHUNK
     int32_t nchunk;          // k_max / CHUNK
     int32_t block;
@@ -130,15 +140,21 @@ struct StepArgs {
     uint64_t seed;
 };
 
-// host-side launchers (vbc_kernels.hip)
-hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, const double *x,
-                            const double *v, const int32_t *type, uint64_t step0, hipStream_t s,
-                            int64_t n_in, int64_t in_off);
-hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int64_t slot_lo,
-                            int64_t nslot, int64_t out_off, int64_t out_stride, double *x,
-                            double *v, hipStream_t s);
-hipError_t launch_flags(const Buffers &B, const Launch &P, uint32_t bits, bool set, hipStream_t s);
-hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, hipStream_t s);
+// host-side launchers (vbc_kernels.hip).  Brick kernels cover the bricks
+// [P.b_lo, P.b_lo + P.nb_launch).
+hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
+                            const double *x, const double *v, const int32_t *type,
+                            int64_t in_off, int64_t in_stride, uint64_t step0, hipStream_t s);
+hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int r, int64_t nslot,
+                            int64_t out_off, int64_t out_stride, double *x, double *v,
+                            hipStream_t s);
+hipError_t launch_flags(const Buffers &B, int r_lo, int r_n, uint32_t bits, bool set,
+                        hipStream_t s);
+hipError_t launch_admit(const Buffers &B, int r, int64_t nthreads, hipStream_t s);
+hipError_t launch_retire(const Buffers &B, int r, int b_off, int nbrick, hipStream_t s);
+hipError_t launch_stamp(const Buffers &B, hipStream_t s);
+hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
+                             hipStream_t s);
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
                         hipStream_t s);

@@ -53,39 +53,17 @@ __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 __device__ __forceinline__ float clamp01(float u) { return __builtin_amdgcn_fmed3f(u, 0.0f, 1.0f); }
 __device__ __forceinline__ double clamp01(double u) { return fmin(fmax(u, 0.0), 1.0); }
 
-template <class F>
-__device__ __forceinline__ int bsearch_last(int nrep, F key, int64_t v)
-{
-    int lo = 0, hi = nrep - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (key(mid) <= v) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int rep_of_slot(const RepDev *R, int nrep, int64_t i)
-{
-    return bsearch_last(nrep, [&](int k) { return R[k].p_off; }, i);
-}
-__device__ __forceinline__ int rep_of_caller(const RepDev *R, int nrep, int64_t g)
-{
-    return bsearch_last(nrep, [&](int k) { return R[k].o_off; }, g);
-}
-__device__ __forceinline__ int rep_of_brick(const RepDev *R, int nrep, int b)
-{
-    return bsearch_last(nrep, [&](int k) { return (int64_t)R[k].b_off; }, b);
-}
-
 // Map workgroups to bricks so that consecutive bricks (which share halo cells) land on
 // the same XCD: workgroups are dealt round-robin over the 8 XCDs, so workgroup g runs on
 // XCD g % 8; give that XCD a contiguous run of bricks.  The grid is padded to a multiple
-// of 8 and the map is a bijection on [0, grid).
-__device__ __forceinline__ int brick_of_block()
+// of 8 and the map is a bijection on [0, grid).  A launch covers the bricks
+// [b_lo, b_lo + nb_launch) (all bricks, or those of one replica); -1 = padding.
+__device__ __forceinline__ int brick_of_block(const Launch &P)
 {
     int G = gridDim.x;
     int g = blockIdx.x;
-    return (g & 7) * (G >> 3) + (g >> 3);
+    int k = (g & 7) * (G >> 3) + (g >> 3);
+    return k < P.nb_launch ? P.b_lo + k : -1;
 }
 
 // Smooth step of eq. (omega) and its derivative, in FP64 (used for the switching factor).
@@ -348,23 +326,22 @@ __device__ __forceinline__ void stage_map(const Buffers &B, int b, int stage_cap
 // state in / out, flags
 // ---------------------------------------------------------------------------
 
-// Caller-order input into the live arrays at slot p_off + tag (the unsorted layout that
-// the next full build starts from).
-__global__ void k_set_state(Buffers B, int nrep, int64_t S_, int cur, int64_t in_off,
-                            int64_t n_in, const double *__restrict__ x,
+// Caller-order input of replica r (element tag at in_off + tag of each stride-in_stride
+// component array) into the live arrays at slot p_off + tag: the unsorted layout that the
+// next full build starts from.
+__global__ void k_set_state(Buffers B, int64_t S_, int cur, int r, int64_t in_off,
+                            int64_t in_stride, const double *__restrict__ x,
                             const double *__restrict__ v, const int32_t *__restrict__ type,
                             uint64_t step0)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_in) return;
-    int64_t g = in_off + i;
-    int r = rep_of_caller(B.reps, nrep, g);
     const RepDev &R = B.reps[r];
-    int64_t tg = g - R.o_off;
+    int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tg >= R.n) return;
+    int64_t i = in_off + tg;
     int64_t d = R.p_off + tg;
     for (int a = 0; a < 3; ++a) {
-        B.x[cur][a * S_ + d] = x[a * n_in + i];
-        B.v[a * S_ + d] = v ? v[a * n_in + i] : 0.0;
+        B.x[cur][a * S_ + d] = x[a * in_stride + i];
+        B.v[a * S_ + d] = v ? v[a * in_stride + i] : 0.0;
     }
     B.tag[d] = (int32_t)tg;
     int ty = type ? type[i] : 0;
@@ -375,30 +352,105 @@ __global__ void k_set_state(Buffers B, int nrep, int64_t S_, int cur, int64_t in
     }
 }
 
-__global__ void k_get_state(Buffers B, int nrep, int64_t S_, int cur, int64_t slot_lo,
-                            int64_t nslot, int64_t out_off, int64_t out_stride,
-                            double *__restrict__ x, double *__restrict__ v)
+// Live state of replica r out in caller order (element out_off + tag).
+__global__ void k_get_state(Buffers B, int64_t S_, int cur, int r, int64_t out_off,
+                            int64_t out_stride, double *__restrict__ x, double *__restrict__ v)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nslot) return;
-    int64_t slot = slot_lo + k;
-    int r = rep_of_slot(B.reps, nrep, slot);
     const RepDev &R = B.reps[r];
-    int64_t loc = slot - R.p_off;
-    int lb = (int)(loc / R.bcap);
-    if (lb >= R.nbrick || loc - (int64_t)lb * R.bcap >= B.bcnt[0][R.b_off + lb]) return;
-    int64_t dst = R.o_off + B.tag[slot] - out_off;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)R.nbrick * R.bcap) return;
+    int lb = (int)(k / R.bcap);
+    if (k - (int64_t)lb * R.bcap >= B.bcnt[0][R.b_off + lb]) return;
+    int64_t slot = R.p_off + k;
+    int64_t dst = out_off + B.tag[slot];
     for (int a = 0; a < 3; ++a) {
         if (x) x[a * out_stride + dst] = wrap1(B.x[cur][a * S_ + slot], R.L[a]);
         if (v) v[a * out_stride + dst] = B.v[a * S_ + slot];
     }
 }
 
-__global__ void k_flags(Buffers B, int nrep, uint32_t bits, int set)
+__global__ void k_flags(Buffers B, int r_lo, int r_n, uint32_t bits, int set)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrep) return;
+    if (r >= r_n) return;
+    r += r_lo;
     if (set) B.flags[r] |= bits; else B.flags[r] &= ~bits;
+}
+
+// Rank of a cell in the brick-major order (bricks x-fastest, cells x-fastest inside a
+// brick; edge bricks are cut by the box): every brick before brick (bx, by, bz) covers,
+// whole, the z-slabs below its first cell, the rows below it in its own slab and the
+// columns before it in its own row.
+__device__ __forceinline__ int32_t brick_major_rank(const RepDev &R, const int g[3])
+{
+    int c0[3], e[3], l[3];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = g[a] / R.bd[a] * R.bd[a];
+        e[a] = min(R.bd[a], R.nc[a] - c0[a]);
+        l[a] = g[a] - c0[a];
+    }
+    int64_t rank0 = (int64_t)c0[2] * R.nc[0] * R.nc[1] + (int64_t)c0[1] * R.nc[0] * e[2] +
+                    (int64_t)c0[0] * e[1] * e[2];
+    return (int32_t)(rank0 + l[0] + e[0] * (l[1] + e[1] * l[2]));
+}
+
+// A replica enters the workspace: its static tables (brick owner, brick-major cell ranks)
+// and cleared per-brick, per-cell and per-replica state.
+__global__ void k_admit(Buffers B, int r)
+{
+    const RepDev &R = B.reps[r];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < R.nbrick) {
+        int lb = (int)t, b = R.b_off + lb;
+        int g[3] = {lb % R.nb[0] * R.bd[0], lb / R.nb[0] % R.nb[1] * R.bd[1],
+                    lb / (R.nb[0] * R.nb[1]) * R.bd[2]};
+        B.brick_rep[b] = r;
+        B.brick_rank0[b] = brick_major_rank(R, g);
+        B.bcnt[0][b] = 0;
+        B.bcnt[1][b] = 0;
+        B.bfill[b] = 0;
+        B.stotal[b] = 0;
+        B.win[b] = 0;
+        for (int k = 0; k < 8; ++k) B.part[(size_t)b * 8 + k] = 0.0;
+        B.bevals[b] = 0ull;
+        B.bentries[b] = 0u;
+    }
+    if (t < R.ncell) {
+        int c = (int)t;
+        int g[3] = {c % R.nc[0], c / R.nc[0] % R.nc[1], c / (R.nc[0] * R.nc[1])};
+        int64_t k = R.c_off + c;
+        B.cell_rank[k] = brick_major_rank(R, g);
+        B.cstart[0][k] = 0;
+        B.cstart[1][k] = 0;
+        B.ccnt[0][k] = 0;
+        B.ccnt[1][k] = 0;
+    }
+    if (t == 0) {
+        B.flags[r] = 0u;
+        B.step[r] = 0ull;
+        for (int k = 0; k < 4; ++k) B.stats[4 * r + k] = 0ull;
+    }
+}
+
+// A replica leaves: its bricks become free (brick kernels skip them) and its descriptor
+// empty (reductions over it give zeros).
+__global__ void k_retire(Buffers B, int r, int b_off, int nbrick)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nbrick) B.brick_rep[b_off + t] = -1;
+    if (t == 0) {
+        B.reps[r].n = 0;
+        B.reps[r].nbrick = 0;
+        B.reps[r].ncell = 0;
+    }
+}
+
+// Device time stamp at the end of a step (stream order: after every kernel of the step).
+__global__ void k_stamp(Buffers B, uint32_t mask)
+{
+    unsigned long long k = B.stamp_n[0];
+    B.stamps[k & mask] = wall_clock64();
+    B.stamp_n[0] = k + 1ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -481,15 +533,14 @@ __device__ __forceinline__ int local_cell(const RepDev &R, const StageHdr &S, co
     return l[0] + S.e[0] * (l[1] + S.e[1] * l[2]);
 }
 
-// Full build, part 1: bin unsorted particles into per-brick buckets.
-__global__ void k_gbin(Buffers B, int nrep, int64_t S_, int64_t ntot, int cur)
+// Full build, part 1: bin the unsorted particles of replica r into per-brick buckets.
+__global__ void k_gbin(Buffers B, int64_t S_, int cur, int r)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntot) return;
-    int r = rep_of_caller(B.reps, nrep, g);
     const RepDev &R = B.reps[r];
+    int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tg >= R.n) return;
     if (!(B.flags[r] & FLAG_FULL)) return;
-    int64_t d = R.p_off + (g - R.o_off);
+    int64_t d = R.p_off + tg;
     int c[3];
     bool bad = false;
     for (int a = 0; a < 3; ++a) {
@@ -516,9 +567,10 @@ __global__ void k_gsort(Buffers B, Launch P, int cur)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     if (!(B.flags[r] & FLAG_FULL)) return;
     int lb = b - R.b_off;
@@ -561,9 +613,10 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ int nmem_s;
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     uint32_t fl = B.flags[r];
     if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
@@ -622,9 +675,10 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ unsigned long long lost_sum, ent_sum;
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     if (!(B.flags[r] & (VBC_FLAG_REBUILD | FLAG_FULL))) return;
     int lb = b - R.b_off;
@@ -885,9 +939,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     __shared__ int any_win;
     __shared__ unsigned long long ev_sum;
     __shared__ PairR<Real> pt[MAXT * MAXT];
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
@@ -1001,10 +1056,10 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ int nw;
     int *wl = (int *)smem;  // [bcap] own particles inside a switching window
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    if (!B.win[b]) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0 || !B.win[b]) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     const int64_t S_ = P.nslots;
@@ -1124,9 +1179,10 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ double red[8][1024 / VBC_WAVE];
     __shared__ int moved;
-    int b = brick_of_block();
-    if (b >= P.nbrick_tot) return;
-    int r = rep_of_brick(B.reps, P.nrep, b);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     R4 *spos = (R4 *)smem;
@@ -1158,6 +1214,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
 
     const PairR<Real> p0 = pt[0];
     const uint64_t step = B.step[r];
+    const uint64_t key = st.seed + R.seed;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
     bool bad = false, mv = false;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -1279,7 +1336,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         } else {
             double vv[3] = {B.v[i], B.v[S_ + i], B.v[2 * S_ + i]};
             double xx[3] = {xi_[0], xi_[1], xi_[2]};
-            integrate_one(st, mode, false, F, vv, xx, st.seed, (uint64_t)tg, step);
+            integrate_one(st, mode, false, F, vv, xx, key, (uint64_t)tg, step);
             for (int a = 0; a < 3; ++a) B.v[a * S_ + i] = vv[a];
             if (mode == MODE_LAST) {
                 for (int a = 0; a < 3; ++a) B.Fst[a * S_ + i] = F[a];
@@ -1314,31 +1371,40 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     }
 }
 
-// Opening half-kick and drift of the first step of a call, from the forces kept in Fst.
-__global__ void k_kick_drift(Buffers B, int nrep, int64_t S_, int cur, StepArgs st)
+// Opening half-kick and drift of the first step of a call, from the forces kept in Fst;
+// one workgroup per brick.
+__global__ void k_kick_drift(Buffers B, Launch P, int cur, StepArgs st)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S_) return;
-    int r = rep_of_slot(B.reps, nrep, i);
+    int b = brick_of_block(P);
+    if (b < 0) return;
+    int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
-    int64_t loc = i - R.p_off;
-    int lb = (int)(loc / R.bcap);
-    if (lb >= R.nbrick || loc - (int64_t)lb * R.bcap >= B.bcnt[0][R.b_off + lb]) return;
-    double F[3], v[3], x[3];
-    for (int a = 0; a < 3; ++a) {
-        F[a] = B.Fst[a * S_ + i];
-        v[a] = B.v[a * S_ + i];
-        x[a] = B.x[cur][a * S_ + i];
+    const int64_t S_ = P.nslots;
+    const int64_t base = R.p_off + (int64_t)(b - R.b_off) * R.bcap;
+    const int nown = B.bcnt[0][b];
+    const uint64_t key = st.seed + R.seed, step = B.step[r];
+    bool far = false;
+    for (int t = threadIdx.x; t < nown; t += blockDim.x) {
+        int64_t i = base + t;
+        double F[3], v[3], x[3];
+        for (int a = 0; a < 3; ++a) {
+            F[a] = B.Fst[a * S_ + i];
+            v[a] = B.v[a * S_ + i];
+            x[a] = B.x[cur][a * S_ + i];
+        }
+        integrate_one(st, MODE_MID, true, F, v, x, key, (uint64_t)B.tag[i], step);
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            B.v[a * S_ + i] = v[a];
+            B.x[cur ^ 1][a * S_ + i] = x[a];
+            double dd = x[a] - B.xref[a * S_ + i];
+            d2 += dd * dd;
+        }
+        far = far || d2 > R.disp2;
     }
-    integrate_one(st, MODE_MID, true, F, v, x, st.seed, (uint64_t)B.tag[i], B.step[r]);
-    double d2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        B.v[a * S_ + i] = v[a];
-        B.x[cur ^ 1][a * S_ + i] = x[a];
-        double dd = x[a] - B.xref[a * S_ + i];
-        d2 += dd * dd;
-    }
-    if (d2 > R.disp2) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
+    if (__syncthreads_or(far) && threadIdx.x == 0)
+        atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
 }
 
 // Per-replica totals from the per-brick partial sums, in brick order.
@@ -1421,48 +1487,68 @@ size_t lds_bytes_force(const Launch &P)
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 48 : 24);
 }
 
-hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, const double *x,
-                            const double *v, const int32_t *type, uint64_t step0, hipStream_t s,
-                            int64_t n_in, int64_t in_off)
+hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
+                            const double *x, const double *v, const int32_t *type,
+                            int64_t in_off, int64_t in_stride, uint64_t step0, hipStream_t s)
 {
-    if (n_in <= 0) return hipSuccess;
-    k_set_state<<<blocks_for(n_in, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, in_off, n_in, x, v,
-                                                       type, step0);
+    if (n <= 0) return hipSuccess;
+    k_set_state<<<blocks_for(n, 256), 256, 0, s>>>(B, P.nslots, cur, r, in_off, in_stride, x, v,
+                                                    type, step0);
     return hipGetLastError();
 }
 
-hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int64_t slot_lo,
-                            int64_t nslot, int64_t out_off, int64_t out_stride, double *x,
-                            double *v, hipStream_t s)
+hipError_t launch_get_state(const Buffers &B, const Launch &P, int cur, int r, int64_t nslot,
+                            int64_t out_off, int64_t out_stride, double *x, double *v,
+                            hipStream_t s)
 {
     if (nslot <= 0) return hipSuccess;
-    k_get_state<<<blocks_for(nslot, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, slot_lo, nslot,
-                                                        out_off, out_stride, x, v);
+    k_get_state<<<blocks_for(nslot, 256), 256, 0, s>>>(B, P.nslots, cur, r, out_off, out_stride,
+                                                        x, v);
     return hipGetLastError();
 }
 
-hipError_t launch_flags(const Buffers &B, const Launch &P, uint32_t bits, bool set, hipStream_t s)
+hipError_t launch_flags(const Buffers &B, int r_lo, int r_n, uint32_t bits, bool set,
+                        hipStream_t s)
 {
-    k_flags<<<blocks_for(P.nrep, 64), 64, 0, s>>>(B, P.nrep, bits, set ? 1 : 0);
+    if (r_n <= 0) return hipSuccess;
+    k_flags<<<blocks_for(r_n, 64), 64, 0, s>>>(B, r_lo, r_n, bits, set ? 1 : 0);
     return hipGetLastError();
 }
 
-// Replicas flagged FULL are binned and sorted from caller-order input; replicas with a
-// pending displacement rebuild take the incremental path in the same pass (k_resort skips
-// FULL replicas, k_gbin / k_gsort skip the others), so one k_nlist serves both.
-hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, hipStream_t s)
+hipError_t launch_admit(const Buffers &B, int r, int64_t nthreads, hipStream_t s)
 {
-    k_gbin<<<blocks_for(P.ntot, 256), 256, 0, s>>>(B, P.nrep, P.nslots, P.ntot, cur);
-    k_gsort<<<brick_grid(P.nbrick_tot), P.block, sort_bytes(P), s>>>(B, P, cur);
-    k_resort<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
-    k_nlist<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
+    k_admit<<<blocks_for(std::max<int64_t>(nthreads, 1), 256), 256, 0, s>>>(B, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_retire(const Buffers &B, int r, int b_off, int nbrick, hipStream_t s)
+{
+    k_retire<<<blocks_for(std::max(nbrick, 1), 256), 256, 0, s>>>(B, r, b_off, nbrick);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(const Buffers &B, hipStream_t s)
+{
+    k_stamp<<<1, 1, 0, s>>>(B, (uint32_t)(STAMP_CAP - 1));
+    return hipGetLastError();
+}
+
+// Full build of replica r (P covering its bricks): bin and sort it from caller-order
+// input, then build its list.  k_resort skips FULL replicas, so the same two-kernel tail
+// as an incremental rebuild serves.
+hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
+                             hipStream_t s)
+{
+    if (n > 0) k_gbin<<<blocks_for(n, 256), 256, 0, s>>>(B, P.nslots, cur, r);
+    k_gsort<<<brick_grid(P.nb_launch), P.block, sort_bytes(P), s>>>(B, P, cur);
+    k_nlist<<<brick_grid(P.nb_launch), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
     return hipGetLastError();
 }
 
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    k_resort<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
-    k_nlist<<<brick_grid(P.nbrick_tot), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
+    k_resort<<<brick_grid(P.nb_launch), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
+    k_nlist<<<brick_grid(P.nb_launch), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
     return hipGetLastError();
 }
 
@@ -1470,7 +1556,7 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
                         hipStream_t s)
 {
     size_t lds = lds_bytes_count(P);
-    unsigned g = brick_grid(P.nbrick_tot);
+    unsigned g = brick_grid(P.nb_launch);
     bool multi = P.ntypes_max > 1;
     if (P.precision == VBC_FP64) {
         if (multi) k_count<double, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
@@ -1484,7 +1570,7 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
 
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    unsigned g = brick_grid(P.nbrick_tot);
+    unsigned g = brick_grid(P.nb_launch);
     bool multi = P.ntypes_max > 1;
     const int bs = 256;
     size_t lds = lds_bytes_embed(P);
@@ -1503,7 +1589,7 @@ static void launch_force_t(const Buffers &B, const Launch &P, int cur, Mode mode
                            const StepArgs &st, double *F_out, double *e_out, hipStream_t s)
 {
     size_t lds = lds_bytes_force(P);
-    unsigned g = brick_grid(P.nbrick_tot);
+    unsigned g = brick_grid(P.nb_launch);
     if (thermo)
         k_force<Real, MULTI, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out);
     else
@@ -1533,7 +1619,7 @@ hipError_t launch_reduce(const Buffers &B, const Launch &P, double *UW, hipStrea
 hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const StepArgs &st,
                              hipStream_t s)
 {
-    k_kick_drift<<<blocks_for(P.nslots, 256), 256, 0, s>>>(B, P.nrep, P.nslots, cur, st);
+    k_kick_drift<<<brick_grid(P.nb_launch), 256, 0, s>>>(B, P, cur, st);
     return hipGetLastError();
 }
 

@@ -26,7 +26,9 @@ NVE, LANGEVIN = 0, 1
 # every symbol include/vbc.h declares
 EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", "vbc_set_state",
            "vbc_get_state", "vbc_build_nlist", "vbc_count", "vbc_force", "vbc_step", "vbc_check",
-           "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read")
+           "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read",
+           "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
+           "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -38,7 +40,7 @@ class ReplicaDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("L", C.c_double * 3), ("ntypes", C.c_int32),
                 ("params", C.POINTER(PairParams)), ("count_mask", C.POINTER(C.c_uint32)),
                 ("skin", C.c_double), ("chain_len", C.c_int32), ("k_bond", C.c_double),
-                ("r0_bond", C.c_double)]
+                ("r0_bond", C.c_double), ("seed", C.c_uint64)]
 
 
 class Options(C.Structure):
@@ -49,6 +51,18 @@ class Options(C.Structure):
 class Integrator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("kT", C.c_double),
                 ("gamma", C.c_double), ("seed", C.c_uint64)]
+
+
+class PoolCaps(C.Structure):
+    _fields_ = [("max_replicas", C.c_int32), ("max_types", C.c_int32), ("max_particles", C.c_int64),
+                ("max_slots", C.c_int64), ("max_bricks", C.c_int32), ("max_cells", C.c_int32),
+                ("max_bcap", C.c_int32), ("chains", C.c_int32)]
+
+
+class Footprint(C.Structure):
+    _fields_ = [("slots", C.c_int64), ("bricks", C.c_int32), ("cells", C.c_int32),
+                ("bcap", C.c_int32), ("k_max", C.c_int32), ("stage_cap", C.c_int32),
+                ("brick", C.c_int32), ("bytes", C.c_size_t)]
 
 
 class Stats(C.Structure):
@@ -89,6 +103,15 @@ def lib():
             "vbc_get_stats": [vp, vp, C.POINTER(Stats)],
             "vbc_profile": [vp, i32, i32],
             "vbc_profile_read": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+            "vbc_replica_footprint": [C.POINTER(ReplicaDesc), C.POINTER(Options), C.POINTER(Footprint)],
+            "vbc_pool_workspace_size": [C.POINTER(PoolCaps), C.POINTER(Options), C.POINTER(C.c_size_t)],
+            "vbc_pool_create": [C.POINTER(PoolCaps), C.POINTER(Options), vp, C.c_size_t, vp, C.POINTER(vp)],
+            "vbc_admit": [vp, C.POINTER(ReplicaDesc), dp, dp, dp, u64, vp, C.POINTER(C.c_int32)],
+            "vbc_retire": [vp, i32, vp],
+            "vbc_replica_info": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+            "vbc_stamps": [vp, i32, vp],
+            "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -122,12 +145,14 @@ def _pair_array(params, ntypes):
     return arr
 
 
-def replica(n, L, params, mask=None, skin=0.4, chain_len=0, k_bond=0.0, r0_bond=1.0):
-    """Description of one replica (host side).  params: dict or list of ntypes^2 dicts."""
+def replica(n, L, params, mask=None, skin=0.4, chain_len=0, k_bond=0.0, r0_bond=1.0, seed=0):
+    """Description of one replica (host side).  params: dict or list of ntypes^2 dicts;
+    seed is added to the integrator's seed to key this replica's noise."""
     ntypes = 1 if isinstance(params, dict) else int(round(len(params) ** 0.5))
     return dict(n=int(n), L=np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy(),
                 params=params, ntypes=ntypes, mask=None if mask is None else np.asarray(mask, np.uint32),
-                skin=float(skin), chain_len=int(chain_len), k_bond=float(k_bond), r0_bond=float(r0_bond))
+                skin=float(skin), chain_len=int(chain_len), k_bond=float(k_bond), r0_bond=float(r0_bond),
+                seed=int(seed))
 
 
 def _descs(reps):
@@ -152,6 +177,7 @@ def _descs(reps):
         d.chain_len = r["chain_len"]
         d.k_bond = r["k_bond"]
         d.r0_bond = r["r0_bond"]
+        d.seed = r.get("seed", 0) & 0xFFFFFFFFFFFFFFFF
     return arr, keep
 
 
@@ -182,34 +208,23 @@ def _soa(t, n, torch, device, dtype):
     return t.contiguous()
 
 
-class System:
-    """One or more replicas resident on one GPU behind a libvbc handle."""
+class _Handle:
+    """Calls shared by a fixed replica set (System) and a pool (Pool)."""
 
-    def __init__(self, reps, precision="fp64", k_max=0, brick=0, block=0, stage_cap=0,
-                 device="cuda"):
+    nslot = 0      # replica slots (reports and UW rows)
+    stride = 0     # caller-order stride of per-particle arrays
+
+    def _init_common(self, device):
         import torch
 
         self.torch = torch
-        if isinstance(reps, dict):
-            reps = [reps]
-        self.reps = reps
-        self.nrep = len(reps)
-        self.ntot = sum(r["n"] for r in reps)
-        self.offsets = np.concatenate([[0], np.cumsum([r["n"] for r in reps])]).astype(np.int64)
         self.device = torch.device(device)
-        arr, keep = _descs(reps)
-        o = _options(precision, k_max, brick, block, stage_cap)
-        n = C.c_size_t(0)
-        _check(lib().vbc_workspace_size(arr, self.nrep, C.byref(o), C.byref(n)))
-        self.ws_bytes = int(n.value)
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
-        h = C.c_void_p()
-        _check(lib().vbc_create(arr, self.nrep, C.byref(o), C.c_void_p(self._ws_ptr),
-                                C.c_size_t(self.ws_bytes), self._stream(), C.byref(h)))
-        self.h = h
-        self.precision = precision
+        self.h = None
+
+    def _alloc_ws(self, nbytes):
+        self.ws_bytes = int(nbytes)
+        self.ws = self.torch.empty(self.ws_bytes + 256, dtype=self.torch.uint8, device=self.device)
+        self._ws_ptr = (self.ws.data_ptr() + 255) & ~255
 
     # -- plumbing -----------------------------------------------------------
     def _stream(self):
@@ -235,23 +250,30 @@ class System:
         return dict(precision=o.precision, k_max=o.k_max, brick=o.brick, block=o.block,
                     stage_cap=o.stage_cap)
 
+    def _n_of(self, rep):
+        raise NotImplementedError
+
     # -- state --------------------------------------------------------------
-    def set_state(self, x, v=None, types=None, rep=-1, step0=0):
+    def _state_tensors(self, x, v, types, n):
         torch = self.torch
-        n = self.ntot if rep < 0 else self.reps[rep]["n"]
         xs = _soa(x, n, torch, self.device, torch.float64)
         vs = _soa(v, n, torch, self.device, torch.float64) if v is not None else None
         ts = None
         if types is not None:
             ts = (torch.from_numpy(np.ascontiguousarray(types)) if isinstance(types, np.ndarray)
                   else types).to(device=self.device, dtype=torch.int32).contiguous()
+        return xs, vs, ts
+
+    def set_state(self, x, v=None, types=None, rep=-1, step0=0):
+        n = self.stride if rep < 0 else self._n_of(rep)
+        xs, vs, ts = self._state_tensors(x, v, types, n)
         self._ok(lib().vbc_set_state(self.h, rep, _ptr(xs), _ptr(vs), _ptr(ts), int(step0),
                                      self._stream()))
         self._keep = (xs, vs, ts)  # alive until the copy kernel has run
 
     def get_state(self, rep=-1):
         torch = self.torch
-        n = self.ntot if rep < 0 else self.reps[rep]["n"]
+        n = self.stride if rep < 0 else self._n_of(rep)
         x = torch.empty((3, n), dtype=torch.float64, device=self.device)
         v = torch.empty((3, n), dtype=torch.float64, device=self.device)
         self._ok(lib().vbc_get_state(self.h, rep, _ptr(x), _ptr(v), self._stream()))
@@ -262,15 +284,15 @@ class System:
         self._ok(lib().vbc_build_nlist(self.h, self._stream()))
 
     def count(self):
-        n = self.torch.empty(self.ntot, dtype=self.torch.float64, device=self.device)
+        n = self.torch.empty(self.stride, dtype=self.torch.float64, device=self.device)
         self._ok(lib().vbc_count(self.h, _ptr(n), self._stream()))
         return n
 
     def force(self, energies=True):
         torch = self.torch
-        F = torch.empty((3, self.ntot), dtype=torch.float64, device=self.device)
-        e = torch.empty(self.ntot, dtype=torch.float64, device=self.device) if energies else None
-        UW = torch.empty((self.nrep, 8), dtype=torch.float64, device=self.device) if energies else None
+        F = torch.empty((3, self.stride), dtype=torch.float64, device=self.device)
+        e = torch.empty(self.stride, dtype=torch.float64, device=self.device) if energies else None
+        UW = torch.empty((self.nslot, 8), dtype=torch.float64, device=self.device) if energies else None
         self._ok(lib().vbc_force(self.h, _ptr(F), _ptr(e), _ptr(UW), self._stream()))
         return F.t(), e, UW
 
@@ -281,14 +303,14 @@ class System:
         self._ok(lib().vbc_step(self.h, int(nsteps), C.byref(it), self._stream()))
 
     def check(self, raise_on_error=True):
-        flags = (C.c_uint32 * self.nrep)()
+        flags = (C.c_uint32 * self.nslot)()
         st = lib().vbc_check(self.h, self._stream(), flags)
         if raise_on_error:
             self._ok(st)
         return st, [int(f) for f in flags]
 
     def stats(self):
-        out = (Stats * self.nrep)()
+        out = (Stats * self.nslot)()
         self._ok(lib().vbc_get_stats(self.h, self._stream(), out))
         return [dict(builds=o.builds, list_entries=o.list_entries, pair_evals=o.pair_evals,
                      evals=o.evals) for o in out]
@@ -302,9 +324,20 @@ class System:
         self._ok(lib().vbc_profile_read(self.h, self._stream(), ms, n))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
+    def stamps(self, enable=True):
+        self._ok(lib().vbc_stamps(self.h, 1 if enable else 0, self._stream()))
+
+    def stamps_read(self, cap=1 << 16):
+        """Device clock at the end of each stamped step since the last read (seconds)."""
+        buf = (C.c_uint64 * cap)()
+        n = C.c_int64(0)
+        hz = C.c_double(0.0)
+        self._ok(lib().vbc_stamps_read(self.h, self._stream(), buf, int(cap), C.byref(n), C.byref(hz)))
+        return np.array(buf[: n.value], dtype=np.float64) / hz.value
+
     def nlist_pairs(self, rep=0, cap=None):
         torch = self.torch
-        n = self.reps[rep]["n"]
+        n = self._n_of(rep)
         if cap is None:
             cap = n * self.options()["k_max"]
         pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
@@ -312,3 +345,103 @@ class System:
         self._ok(lib().vbc_get_nlist(self.h, rep, _ptr(pairs), int(cap), _ptr(cnt), self._stream()))
         c = int(cnt.item())
         return pairs[: min(c, cap)].cpu().numpy(), c
+
+
+class System(_Handle):
+    """One or more replicas resident on one GPU behind a libvbc handle (vbc_create)."""
+
+    def __init__(self, reps, precision="fp64", k_max=0, brick=0, block=0, stage_cap=0,
+                 device="cuda"):
+        self._init_common(device)
+        if isinstance(reps, dict):
+            reps = [reps]
+        self.reps = reps
+        self.nrep = self.nslot = len(reps)
+        self.ntot = self.stride = sum(r["n"] for r in reps)
+        self.offsets = np.concatenate([[0], np.cumsum([r["n"] for r in reps])]).astype(np.int64)
+        arr, keep = _descs(reps)
+        o = _options(precision, k_max, brick, block, stage_cap)
+        n = C.c_size_t(0)
+        _check(lib().vbc_workspace_size(arr, self.nrep, C.byref(o), C.byref(n)))
+        self._alloc_ws(n.value)
+        h = C.c_void_p()
+        _check(lib().vbc_create(arr, self.nrep, C.byref(o), C.c_void_p(self._ws_ptr),
+                                C.c_size_t(self.ws_bytes), self._stream(), C.byref(h)))
+        self.h = h
+        self.precision = precision
+
+    def _n_of(self, rep):
+        return self.reps[rep]["n"]
+
+
+def footprint(rep, precision="fp64", **opts):
+    """Layout of one replica and the workspace bytes it takes (host-only; no GPU needed)."""
+    arr, keep = _descs([rep])
+    o = _options(precision, **opts)
+    fp = Footprint()
+    _check(lib().vbc_replica_footprint(arr, C.byref(o), C.byref(fp)))
+    return dict(slots=int(fp.slots), bricks=int(fp.bricks), cells=int(fp.cells), bcap=int(fp.bcap),
+                k_max=int(fp.k_max), stage_cap=int(fp.stage_cap), brick=int(fp.brick),
+                bytes=int(fp.bytes))
+
+
+def _caps(max_replicas, max_particles, max_slots, max_bricks, max_cells, max_bcap, max_types, chains):
+    c = PoolCaps()
+    c.max_replicas, c.max_types = int(max_replicas), int(max_types)
+    c.max_particles, c.max_slots = int(max_particles), int(max_slots)
+    c.max_bricks, c.max_cells, c.max_bcap = int(max_bricks), int(max_cells), int(max_bcap)
+    c.chains = 1 if chains else 0
+    return c
+
+
+def pool_workspace_size(caps, precision="fp32", **opts):
+    c = _caps(**caps)
+    o = _options(precision, **opts)
+    n = C.c_size_t(0)
+    _check(lib().vbc_pool_workspace_size(C.byref(c), C.byref(o), C.byref(n)))
+    return int(n.value)
+
+
+class Pool(_Handle):
+    """A fixed-capacity pool of replicas that enter (admit) and leave (retire) while the
+    others keep running (vbc_pool_create)."""
+
+    def __init__(self, caps, precision="fp32", k_max=0, stage_cap=0, brick=0, block=0,
+                 device="cuda"):
+        self._init_common(device)
+        self.caps = dict(caps)
+        c = _caps(**caps)
+        self.nslot = c.max_replicas
+        self.stride = c.max_particles
+        o = _options(precision, k_max, brick, block, stage_cap)
+        n = C.c_size_t(0)
+        _check(lib().vbc_pool_workspace_size(C.byref(c), C.byref(o), C.byref(n)))
+        self._alloc_ws(n.value)
+        h = C.c_void_p()
+        _check(lib().vbc_pool_create(C.byref(c), C.byref(o), C.c_void_p(self._ws_ptr),
+                                     C.c_size_t(self.ws_bytes), self._stream(), C.byref(h)))
+        self.h = h
+        self.precision = precision
+        self._keep_admit = {}
+
+    def _n_of(self, rep):
+        return self.info(rep)[0]
+
+    def info(self, rep):
+        n, off = C.c_int64(0), C.c_int64(0)
+        self._ok(lib().vbc_replica_info(self.h, int(rep), C.byref(n), C.byref(off)))
+        return int(n.value), int(off.value)
+
+    def admit(self, rep, x, v=None, types=None, step0=0):
+        """Admit one replica (description from replica()) with its state; returns its slot."""
+        arr, keep = _descs([rep])
+        xs, vs, ts = self._state_tensors(x, v, types, rep["n"])
+        r = C.c_int32(-1)
+        self._ok(lib().vbc_admit(self.h, arr, _ptr(xs), _ptr(vs), _ptr(ts), int(step0),
+                                 self._stream(), C.byref(r)))
+        self._keep_admit[int(r.value)] = (xs, vs, ts)  # alive until the copy kernel has run
+        return int(r.value)
+
+    def retire(self, rep):
+        self._ok(lib().vbc_retire(self.h, int(rep), self._stream()))
+        self._keep_admit.pop(int(rep), None)
