@@ -74,7 +74,7 @@ struct Caps {
 };
 
 struct Offsets {
-    size_t reps, brick_rep, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
+    size_t reps, brick_rep, wl0, wl1, wl_n, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
         bfill, x0, x1, v, Fst, xref, tag, type, lcell, xs, vs, tags, types, lcells, src, inv,
         smap, wmap, stotal, nl, nn, nd, sA, win, part, flags, step, stats, bevals, bentries,
         stamps, stamp_n;
@@ -337,6 +337,9 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
     const size_t nb = (size_t)C.nbrick, nc = (size_t)C.ncell, nr = (size_t)C.nrep;
     o.reps = carve(off, sizeof(RepDev) * nr);
     o.brick_rep = carve(off, sizeof(int32_t) * nb);
+    o.wl0 = carve(off, sizeof(int32_t) * nb);
+    o.wl1 = carve(off, sizeof(int32_t) * nb);
+    o.wl_n = carve(off, sizeof(int32_t) * 2);
     o.cell_rank = carve(off, sizeof(int32_t) * nc);
     o.brick_rank0 = carve(off, sizeof(int32_t) * nb);
     o.cstart0 = carve(off, sizeof(int32_t) * nc);
@@ -386,7 +389,7 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
 size_t footprint_bytes(const RepPlan &rp, int precision, int nchunk, int stage_cap)
 {
     size_t per_slot = 7 * 24 + 5 * 4 + 2 + 16 * (size_t)nchunk + 2 + 8 + (precision == VBC_FP64 ? 16 : 8);
-    size_t per_brick = 4 * 6 + 5 * (size_t)stage_cap + 1 + 64 + 8 + 4;
+    size_t per_brick = 4 * 8 + 5 * (size_t)stage_cap + 1 + 64 + 8 + 4;
     size_t per_cell = 5 * 4;
     return per_slot * (size_t)rp.slots + per_brick * (size_t)rp.R.nbrick +
            per_cell * (size_t)rp.R.ncell + 4 * (size_t)rp.R.n + sizeof(RepDev) + 4 + 8 + 32;
@@ -404,6 +407,7 @@ Launch launch_for(const Caps &C, const vbc_options &opt)
     P.nbrick_tot = C.nbrick;
     P.b_lo = 0;
     P.nb_launch = C.nbrick;
+    P.list = 0;
     P.k_max = opt.k_max;
     P.nchunk = opt.k_max / CHUNK;
     P.block = opt.block;
@@ -422,6 +426,7 @@ Launch restrict_to(const Launch &P, const RepDev &R)
     Launch Q = P;
     Q.b_lo = R.b_off;
     Q.nb_launch = R.nbrick;
+    Q.list = -1;
     return Q;
 }
 
@@ -485,6 +490,9 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     Buffers &B = h->B;
     B.reps = at<RepDev>(d_ws, o.reps);
     B.brick_rep = at<int32_t>(d_ws, o.brick_rep);
+    B.wl[0] = at<int32_t>(d_ws, o.wl0);
+    B.wl[1] = at<int32_t>(d_ws, o.wl1);
+    B.wl_n = at<int32_t>(d_ws, o.wl_n);
     B.cell_rank = at<int32_t>(d_ws, o.cell_rank);
     B.brick_rank0 = at<int32_t>(d_ws, o.brick_rank0);
     B.cstart[0] = at<int32_t>(d_ws, o.cstart0);
@@ -767,6 +775,7 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
                            Caps &C, vbc_options &opt, std::vector<RepPlan> &plans)
 {
     if (!reps || nrep < 1) return fail(VBC_ERR_ARG, "need at least one replica");
+    if (nrep > MAX_REPLICAS) return fail(VBC_ERR_ARG, "at most 1024 replicas per handle");
     vbc_status st = check_options(opt_in, opt);
     if (st != VBC_OK) return st;
     plans.resize(nrep);
@@ -850,8 +859,8 @@ vbc_status vbc_create(const vbc_replica_desc *reps, int32_t nrep, const vbc_opti
 static vbc_status check_caps(const vbc_pool_caps *caps, const vbc_options &opt, Caps &C)
 {
     if (!caps) return fail(VBC_ERR_ARG, "caps is NULL");
-    if (caps->max_replicas < 1 || caps->max_replicas > (1 << 20))
-        return fail(VBC_ERR_ARG, "max_replicas must be 1..2^20");
+    if (caps->max_replicas < 1 || caps->max_replicas > MAX_REPLICAS)
+        return fail(VBC_ERR_ARG, "max_replicas must be 1..1024");
     if (caps->max_types < 1 || caps->max_types > MAXT) return fail(VBC_ERR_ARG, "max_types must be 1..4");
     if (caps->max_particles < 1 || caps->max_slots < caps->max_particles)
         return fail(VBC_ERR_ARG, "need 1 <= max_particles <= max_slots");

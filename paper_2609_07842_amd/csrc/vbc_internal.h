@@ -22,6 +22,7 @@ constexpr int MAXT = 4;          // particle types per replica
 constexpr int MAX_BRICK = 6;     // cells per brick edge
 constexpr int NH_MAX = (MAX_BRICK + 2) * (MAX_BRICK + 2) * (MAX_BRICK + 2);
 constexpr int CHUNK = 8;         // list entries per 16-byte chunk
+constexpr int MAX_REPLICAS = 1024;  // replica slots of one handle
 
 // Derived constants of one type pair.  Everything the kernels need is precomputed on
 // the host in FP64 from vbc_pair_params.
@@ -68,6 +69,8 @@ struct RepDev {
 struct Buffers {
     RepDev *reps;            // [nrep]
     int32_t *brick_rep;      // [nbrick_tot] replica owning each brick, -1 = free
+    int32_t *wl[2];          // [nbrick_tot] work lists: live bricks, bricks due for a rebuild
+    int32_t *wl_n;           // [2] entries of each work list
     int32_t *cell_rank;      // [sum ncell]  cell linear index -> brick-major rank (static)
     int32_t *brick_rank0;    // [nbrick_tot] rank of a brick's first cell (static)
     int32_t *cstart[2];      // [sum ncell] first slot of each cell (by rank)
@@ -113,7 +116,8 @@ struct Launch {
     int64_t nslots;          // slots (sum nbrick * bcap)
     int32_t ncell_tot;
     int32_t nbrick_tot;
-    int32_t b_lo, nb_launch; // bricks one launch covers: [b_lo, b_lo + nb_launch)
+    int32_t b_lo, nb_launch; // bricks one launch covers: [b_lo, b_lo + nb_launch), or
+    int32_t list;            // >= 0: the entries of that work list instead
     int32_t k_max;           // multiple of CHUNK
     int32_t nchunk;          // k_max / CHUNK
     int32_t block;
@@ -141,7 +145,8 @@ struct StepArgs {
 };
 
 // host-side launchers (vbc_kernels.hip).  Brick kernels cover the bricks
-// [P.b_lo, P.b_lo + P.nb_launch).
+// [P.b_lo, P.b_lo + P.nb_launch), or with P.list >= 0 the work lists that launch_rebuild and
+// launch_kick_drift make first.
 hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
                             const double *x, const double *v, const int32_t *type,
                             int64_t in_off, int64_t in_stride, uint64_t step0, hipStream_t s);

@@ -55,15 +55,21 @@ __device__ __forceinline__ double clamp01(double u) { return fmin(fmax(u, 0.0), 
 
 // Map workgroups to bricks so that consecutive bricks (which share halo cells) land on
 // the same XCD: workgroups are dealt round-robin over the 8 XCDs, so workgroup g runs on
-// XCD g % 8; give that XCD a contiguous run of bricks.  The grid is padded to a multiple
-// of 8 and the map is a bijection on [0, grid).  A launch covers the bricks
-// [b_lo, b_lo + nb_launch) (all bricks, or those of one replica); -1 = padding.
-__device__ __forceinline__ int brick_of_block(const Launch &P)
+// XCD g % 8; give that XCD a contiguous run of the T bricks to visit.  The grid is padded
+// to a multiple of 8, at least T.  The bricks are either the contiguous range
+// [b_lo, b_lo + nb_launch) (P.list < 0: all bricks, or one replica's) or the entries of
+// work list P.list, which the step computes on the GPU.  Returns false for a workgroup
+// with nothing to do (padding, or a free brick).
+__device__ __forceinline__ bool resolve_brick(const Launch &P, const Buffers &B, int &b, int &r)
 {
-    int G = gridDim.x;
-    int g = blockIdx.x;
-    int k = (g & 7) * (G >> 3) + (g >> 3);
-    return k < P.nb_launch ? P.b_lo + k : -1;
+    const int g = blockIdx.x, j = g >> 3;
+    const int T = P.list < 0 ? P.nb_launch : B.wl_n[P.list];
+    const int chunk = (T + 7) >> 3;
+    const int k = (g & 7) * chunk + j;
+    if (j >= chunk || k >= T) return false;
+    b = P.list < 0 ? P.b_lo + k : B.wl[P.list][k];
+    r = B.brick_rep[b];
+    return r >= 0;
 }
 
 // Smooth step of eq. (omega) and its derivative, in FP64 (used for the switching factor).
@@ -453,6 +459,48 @@ __global__ void k_stamp(Buffers B, uint32_t mask)
     B.stamp_n[0] = k + 1ull;
 }
 
+// Work lists of the capacity-wide launches, made on the GPU at the start of every step
+// from the replica table: list 0 = every brick of every live replica, list 1 = the bricks
+// of the replicas whose list is due for an incremental rebuild.  Replica slots in order,
+// bricks in order inside a replica, so consecutive entries are neighbouring bricks.
+__global__ void __launch_bounds__(1024) k_worklist(Buffers B, int nrep)
+{
+    __shared__ int pre[2][MAX_REPLICAS + 1];
+    __shared__ int boff[MAX_REPLICAS];
+    __shared__ int tot[2];
+    for (int r = threadIdx.x; r < nrep; r += blockDim.x) {
+        const RepDev &R = B.reps[r];
+        const int nb = R.nbrick;  // 0 for a free slot
+        const uint32_t fl = B.flags[r];
+        pre[0][r] = nb;
+        pre[1][r] = ((fl & VBC_FLAG_REBUILD) && !(fl & FLAG_FULL)) ? nb : 0;
+        boff[r] = R.b_off;
+    }
+    __syncthreads();
+    const int t0 = wave0_exclusive_scan(pre[0], nrep);
+    const int t1 = wave0_exclusive_scan(pre[1], nrep);
+    if (threadIdx.x == 0) {
+        tot[0] = t0;
+        tot[1] = t1;
+        B.wl_n[0] = t0;
+        B.wl_n[1] = t1;
+    }
+    __syncthreads();
+    for (int l = 0; l < 2; ++l) {
+        const int T = tot[l];
+        for (int k = threadIdx.x; k < T; k += blockDim.x) {
+            // the last replica whose first entry is <= k (empty entries share their
+            // successor's start, so the one found has bricks)
+            int lo = 0, hi = nrep - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (pre[l][mid] <= k) lo = mid; else hi = mid - 1;
+            }
+            B.wl[l][k] = boff[lo] + (k - pre[l][lo]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // list build, step 1: the next sorted layout
 // ---------------------------------------------------------------------------
@@ -567,10 +615,8 @@ __global__ void k_gsort(Buffers B, Launch P, int cur)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     if (!(B.flags[r] & FLAG_FULL)) return;
     int lb = b - R.b_off;
@@ -613,10 +659,8 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ int nmem_s;
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     uint32_t fl = B.flags[r];
     if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
@@ -675,10 +719,8 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ unsigned long long lost_sum, ent_sum;
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     if (!(B.flags[r] & (VBC_FLAG_REBUILD | FLAG_FULL))) return;
     int lb = b - R.b_off;
@@ -939,10 +981,8 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     __shared__ int any_win;
     __shared__ unsigned long long ev_sum;
     __shared__ PairR<Real> pt[MAXT * MAXT];
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
@@ -1056,10 +1096,8 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ int nw;
     int *wl = (int *)smem;  // [bcap] own particles inside a switching window
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0 || !B.win[b]) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r) || !B.win[b]) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     const int64_t S_ = P.nslots;
@@ -1179,10 +1217,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ double red[8][1024 / VBC_WAVE];
     __shared__ int moved;
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     R4 *spos = (R4 *)smem;
@@ -1375,10 +1411,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
 // one workgroup per brick.
 __global__ void k_kick_drift(Buffers B, Launch P, int cur, StepArgs st)
 {
-    int b = brick_of_block(P);
-    if (b < 0) return;
-    int r = B.brick_rep[b];
-    if (r < 0) return;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     const int64_t S_ = P.nslots;
     const int64_t base = R.p_off + (int64_t)(b - R.b_off) * R.bcap;
@@ -1545,10 +1579,17 @@ hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, int r, 
     return hipGetLastError();
 }
 
+// Incremental rebuild of the replicas whose REBUILD flag is set.  A capacity-wide launch
+// first makes the step's work lists and visits only the bricks of those replicas.
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    k_resort<<<brick_grid(P.nb_launch), P.block, lds_bytes_sort(P), s>>>(B, P, cur);
-    k_nlist<<<brick_grid(P.nb_launch), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
+    Launch Q = P;
+    if (P.list >= 0) {
+        k_worklist<<<1, 1024, 0, s>>>(B, P.nrep);
+        Q.list = 1;
+    }
+    k_resort<<<brick_grid(Q.nb_launch), Q.block, lds_bytes_sort(Q), s>>>(B, Q, cur);
+    k_nlist<<<brick_grid(Q.nb_launch), Q.block, lds_bytes_nlist(Q), s>>>(B, Q, cur);
     return hipGetLastError();
 }
 
@@ -1619,6 +1660,7 @@ hipError_t launch_reduce(const Buffers &B, const Launch &P, double *UW, hipStrea
 hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const StepArgs &st,
                              hipStream_t s)
 {
+    if (P.list >= 0) k_worklist<<<1, 1024, 0, s>>>(B, P.nrep);
     k_kick_drift<<<brick_grid(P.nb_launch), 256, 0, s>>>(B, P, cur, st);
     return hipGetLastError();
 }

@@ -1,0 +1,298 @@
+"""Continuous-batching request loop over a replica pool (libvbc's vbc_pool_* calls).
+
+Each request is an independent simulation (its own size, valency, well depth, noise
+seed and step count).  Requests wait in a FIFO queue until a replica slot, enough
+particle indices and enough of the HBM budget are free (admission by workspace
+footprint, vbc_replica_footprint); admitted requests run together, as one pool, one
+captured step graph of `steps_per_tick` steps per launch; a request that has done its
+steps has its final state copied out and leaves, and queued requests take its place
+between two launches while the others keep running.
+
+Everything numeric runs in the library's kernels; this module only decides admission
+and ordering, and reads device time stamps (one per step, vbc_stamps) and HIP events
+for the latency figures.  The same loop with at most one live replica is the
+one-at-a-time baseline.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import vbc as _vbc
+from . import workloads as W
+
+
+@dataclass
+class ServerConfig:
+    budget_bytes: int = 2 << 30      # HBM the live replicas may occupy
+    max_replicas: int = 64
+    max_particles: int = 1 << 21
+    precision: str = "fp32"
+    steps_per_tick: int = 8
+    rho_max: float = 0.3             # densest request the pool is laid out for
+    n_range: tuple = (1_000, 200_000)
+    skin: float = 0.4
+    integrator: dict = field(default_factory=lambda: dict(integrator="langevin", dt=0.005,
+                                                          kT=1.0, gamma=0.1, seed=2024))
+    max_inflight: int = 6            # step launches the host may run ahead of the GPU
+    max_active: int = 0              # 0 = no limit beyond the pool; 1 = one at a time
+
+
+def request_desc(req, skin=0.4):
+    """Replica description of a request dict (N, f, E_a, rho, seed)."""
+    L = W.box_length(req["N"], req["rho"])
+    return _vbc.replica(req["N"], L, W.vbc_params(E_a=req["E_a"], f=req["f"]), skin=skin,
+                        seed=req["seed"])
+
+
+def layout_for(cfg: ServerConfig):
+    """List length and staging capacity that cover every request size at the design
+    density (the largest automatic choice over a log grid of sizes), the range of
+    slots-per-brick such requests need, and the smallest workspace bytes per slot."""
+    k_max = stage_cap = bcap_max = 0
+    bcap_min = 1 << 30
+    # a log grid of sizes, plus the sizes just below each change of the cell count per
+    # axis (there the cells are largest and hold the most particles)
+    p = W.vbc_params()
+    rl = max(p["r_r"], p["r_a"], p["r_h"]) + cfg.skin
+    worst = [math.floor(cfg.rho_max * ((nc + 1) * rl) ** 3 * (1 - 1e-6)) for nc in range(3, 1024)]
+    grid = np.concatenate([np.rint(np.geomspace(cfg.n_range[0], cfg.n_range[1], 64)),
+                           [n for n in worst if cfg.n_range[0] <= n <= cfg.n_range[1]]])
+    grid = np.unique(grid.astype(int))
+    descs = [request_desc(dict(N=int(N), f=1.0, E_a=5.0, rho=cfg.rho_max, seed=0), cfg.skin)
+             for N in grid]
+    for d in descs:
+        fp = _vbc.footprint(d, cfg.precision)
+        k_max, stage_cap = max(k_max, fp["k_max"]), max(stage_cap, fp["stage_cap"])
+        bcap_max, bcap_min = max(bcap_max, fp["bcap"]), min(bcap_min, fp["bcap"])
+    per_slot = min(fp["bytes"] / fp["slots"] for fp in
+                   (_vbc.footprint(d, cfg.precision, k_max=k_max, stage_cap=stage_cap) for d in descs))
+    return dict(k_max=k_max, stage_cap=stage_cap, bcap_max=bcap_max, bcap_min=bcap_min,
+                bytes_per_slot=per_slot)
+
+
+class Server:
+    def __init__(self, cfg: ServerConfig | None = None, device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.cfg = cfg or ServerConfig()
+        c = self.cfg
+        lay = layout_for(c)
+        self.k_max, self.stage_cap = lay["k_max"], lay["stage_cap"]
+        # capacities that the byte budget reaches first: a replica's slots cost at least
+        # bytes_per_slot each, and its bricks hold at least bcap_min slots
+        max_slots = int(c.budget_bytes / lay["bytes_per_slot"]) + 1
+        max_bricks = max_slots // lay["bcap_min"] + c.max_replicas
+        caps = dict(max_replicas=c.max_replicas, max_types=1, max_particles=c.max_particles,
+                    max_slots=max(max_slots, c.max_particles), max_bricks=max_bricks,
+                    max_cells=max_bricks * 64, max_bcap=max(lay["bcap_max"], 64), chains=False)
+        self.pool = _vbc.Pool(caps, precision=c.precision, k_max=self.k_max,
+                              stage_cap=self.stage_cap, device=device)
+        self.device = self.pool.device
+        self.stream = torch.cuda.current_stream(self.device)
+        self._warm()
+
+    def _warm(self):
+        """Capture the step graphs (both buffer parities) on a tiny replica."""
+        c = self.cfg
+        req = dict(N=c.n_range[0], f=2.0, E_a=5.0, rho=c.rho_max, seed=1)
+        d = request_desc(req, c.skin)
+        x = W.uniform_positions(req["N"], d["L"][0], 1)
+        r = self.pool.admit(d, x)
+        for n in (c.steps_per_tick, c.steps_per_tick + 1, c.steps_per_tick):
+            self.pool.step(n, **c.integrator)
+        self.pool.check()
+        self.pool.retire(r)
+        self.torch.cuda.synchronize(self.device)
+
+    def footprint(self, req):
+        return _vbc.footprint(request_desc(req, self.cfg.skin), self.cfg.precision,
+                              k_max=self.k_max, stage_cap=self.stage_cap)["bytes"]
+
+    def run(self, requests, arrivals=None, keep_results=False):
+        """Serve `requests` (dicts with N, f, E_a, rho, seed, steps and device tensors x, v
+        of shape (N, 3)); arrivals[k] = seconds after the start at which request k
+        arrives (None: all at once).  Returns per-request timings, per-step latencies and
+        totals."""
+        torch, cfg, pool = self.torch, self.cfg, self.pool
+        S = cfg.steps_per_tick
+        n_req = len(requests)
+        arr = np.zeros(n_req) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
+        order = np.argsort(arr, kind="stable")
+        fps = [self.footprint(q) for q in requests]
+        for k, q in enumerate(requests):
+            if q["steps"] % S:
+                raise ValueError("request steps must be a multiple of steps_per_tick")
+            if fps[k] > cfg.budget_bytes or q["N"] > cfg.max_particles:
+                raise ValueError(f"request {k} can never fit the pool")
+        ev_start = torch.cuda.Event(enable_timing=True)
+        ticks = []                      # (event, first global step)
+        queue = deque()
+        active = {}                     # slot -> [request index, ticks left, first step]
+        used_bytes = used_particles = 0
+        nxt = 0
+        gstep = 0
+        stamps = []
+        admit_t = np.full(n_req, np.nan)
+        first_step = np.zeros(n_req, dtype=np.int64)
+        done_tick = np.zeros(n_req, dtype=np.int64)
+        results = [None] * n_req
+        flagged = []
+
+        def drain_stamps():
+            stamps.append(pool.stamps_read())
+
+        pool.stamps(True)
+        ev_start.record(self.stream)
+        torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
+        since_read = 0
+        while nxt < n_req or queue or active:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arr[order[nxt]] <= now:
+                queue.append(int(order[nxt]))
+                nxt += 1
+            # admission: FIFO, while the head fits
+            while queue:
+                k = queue[0]
+                q = requests[k]
+                if cfg.max_active and len(active) >= cfg.max_active:
+                    break
+                if (len(active) >= cfg.max_replicas or used_bytes + fps[k] > cfg.budget_bytes
+                        or used_particles + q["N"] > cfg.max_particles):
+                    break
+                try:
+                    r = pool.admit(request_desc(q, cfg.skin), q["x"], q["v"])
+                except _vbc.VBCError as e:
+                    if e.status != _vbc.VBC_ERR_CAPACITY:
+                        raise
+                    break  # no contiguous range now: wait for a retirement
+                queue.popleft()
+                active[r] = [k, q["steps"] // S, gstep]
+                admit_t[k] = time.perf_counter() - t0
+                first_step[k] = gstep
+                used_bytes += fps[k]
+                used_particles += q["N"]
+            if not active:
+                if nxt < n_req:
+                    time.sleep(max(0.0, min(arr[order[nxt]] - (time.perf_counter() - t0), 0.01)))
+                continue
+            pool.step(S, **cfg.integrator)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(self.stream)
+            ticks.append((ev, gstep))
+            gstep += S
+            since_read += S
+            finished = []
+            for r, a in active.items():
+                a[1] -= 1
+                if a[1] == 0:
+                    finished.append(r)
+            if finished:
+                st, flags = pool.check(raise_on_error=False)
+                for r in finished:
+                    k = active[r][0]
+                    if flags[r] & ~_vbc.FLAG_REBUILD:
+                        flagged.append((k, flags[r]))
+                    if keep_results:
+                        x, v = pool.get_state(r)
+                        results[k] = (x.clone(), v.clone())
+                    pool.retire(r)
+                    done_tick[k] = len(ticks) - 1
+                    used_bytes -= fps[k]
+                    used_particles -= requests[k]["N"]
+                    del active[r]
+            if since_read > (1 << 15):
+                drain_stamps()
+                since_read = 0
+            if len(ticks) > cfg.max_inflight:
+                ticks[-cfg.max_inflight - 1][0].synchronize()
+        drain_stamps()
+        pool.stamps(False)
+        torch.cuda.synchronize(self.device)
+        t_tick = np.array([ev_start.elapsed_time(ev) * 1e-3 for ev, _ in ticks])
+        st = np.concatenate(stamps) if stamps else np.zeros(0)
+        if len(st) != gstep:
+            raise RuntimeError(f"expected {gstep} step stamps, got {len(st)}")
+        # per-step latency: interval between a request's successive step completions
+        lat = []
+        for k, q in enumerate(requests):
+            g0 = first_step[k]
+            lat.append(np.diff(st[g0:g0 + q["steps"]]))
+        lat = np.concatenate(lat) if lat else np.zeros(0)
+        done = t_tick[done_tick]
+        req_lat = done - arr
+        makespan = float(done.max())
+        n_steps = sum(q["steps"] for q in requests)
+        p_steps = sum(q["steps"] * q["N"] for q in requests)
+        return dict(
+            makespan_s=makespan,
+            requests_per_s=n_req / makespan,
+            request_steps_per_s=n_steps / makespan,
+            particle_steps_per_s=p_steps / makespan,
+            step_latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
+                                 p99=1e3 * float(np.percentile(lat, 99)),
+                                 mean=1e3 * float(lat.mean()), n=int(lat.size)),
+            request_latency_s=dict(p50=float(np.percentile(req_lat, 50)),
+                                   p99=float(np.percentile(req_lat, 99)),
+                                   max=float(req_lat.max())),
+            queue_wait_s=dict(p50=float(np.nanpercentile(admit_t - arr, 50)),
+                              p99=float(np.nanpercentile(admit_t - arr, 99))),
+            global_steps=int(gstep),
+            mean_live=float(n_steps / max(gstep, 1)),
+            flagged=flagged,
+            results=results if keep_results else None,
+        )
+
+
+def make_requests(n=256, seed=5, rho=0.3, steps=1000, device="cuda", n_range=(1_000, 200_000)):
+    """The request stream: sizes, valencies, well depths and noise seeds from the seeded
+    generator, initial states (uniform positions, Maxwell-Boltzmann velocities at kT = 1)
+    placed in device memory up front."""
+    import torch
+
+    reqs = W.serving_requests(n=n, seed=seed, rho=rho, N_min=n_range[0], N_max=n_range[1], steps=steps)
+    for q in reqs:
+        L = W.box_length(q["N"], rho)
+        q["x"] = torch.from_numpy(W.uniform_positions(q["N"], L, q["seed"])).to(device)
+        q["v"] = torch.from_numpy(W.maxwell_boltzmann(q["N"], 1.0, q["seed"] + 1)).to(device)
+    return reqs
+
+
+def poisson_arrivals(reqs, rate):
+    """Arrival times (s) from the stream's unit-rate exponential gaps at `rate` per s."""
+    return np.cumsum([q["gap"] for q in reqs]) / rate
+
+
+def serving_benchmark(n=256, steps=1000, seed=5, load=0.8, cfg=None, log=None):
+    """Capacity with every request queued at t = 0, then Poisson arrivals at `load` x that
+    capacity served batched and one at a time (same arrivals, same pool)."""
+    cfg = cfg or ServerConfig()
+    say = log or (lambda *a: None)
+    reqs = make_requests(n=n, seed=seed, rho=cfg.rho_max, steps=steps, n_range=cfg.n_range)
+    srv = Server(cfg)
+    say(f"[serve] pool: k_max {srv.k_max} stage_cap {srv.stage_cap} "
+        f"workspace {srv.pool.ws_bytes / 2**30:.2f} GiB")
+    sat = srv.run(reqs)
+    say(f"[serve] saturated: {sat['requests_per_s']:.1f} req/s, mean live {sat['mean_live']:.1f}")
+    rate = load * sat["requests_per_s"]
+    arrivals = poisson_arrivals(reqs, rate)
+    batched = srv.run(reqs, arrivals)
+    say(f"[serve] batched at {rate:.1f} req/s: step p99 {batched['step_latency_ms']['p99']:.3f} ms")
+    srv.cfg.max_active = 1
+    single = srv.run(reqs, arrivals)
+    srv.cfg.max_active = 0
+    say(f"[serve] one at a time: {single['requests_per_s']:.1f} req/s")
+    strip = lambda d: {k: v for k, v in d.items() if k not in ("results", "flagged")}
+    return dict(requests=n, steps_per_request=steps, arrival_rate_per_s=rate, load=load,
+                steps_per_tick=cfg.steps_per_tick, budget_bytes=cfg.budget_bytes,
+                max_replicas=cfg.max_replicas, max_particles=cfg.max_particles,
+                mean_N=float(np.mean([q["N"] for q in reqs])),
+                saturated=strip(sat), batched=strip(batched), one_at_a_time=strip(single),
+                flagged=len(sat["flagged"]) + len(batched["flagged"]) + len(single["flagged"]),
+                speedup_throughput=batched["particle_steps_per_s"] / single["particle_steps_per_s"])
