@@ -2,6 +2,7 @@
 """Benchmark of the VBC hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--f 4] [--no-sweep] [--no-cpu]
+                    [--no-serve] [--serve-requests 256]
 
 Workload (default): N = 1,000,000 particles, cubic periodic box at number density 0.5,
 uniform random start, standard VBC(1.5, 2.0, 0) on the polynomial soft core (E_r = 20,
@@ -14,6 +15,12 @@ Prints ONE JSON line.  `value` is pair evaluations per second (ordered pairs ins
 interaction cutoff handled per step, times steps per second); timesteps/s is reported
 beside it.  `roofline` is the dominant kernel's algorithmic bytes per launch over its
 mean duration, timed with HIP events on the launch stream inside the timed region.
+`serving` is the request stream: 256 independent simulations (N log-uniform in
+[10^3, 2x10^5], valency 1..6, well depth 2..10 kT, density 0.3, 1000 Langevin steps each)
+arriving as a Poisson stream at 0.8x the measured batched capacity, served by continuous
+batching in one replica pool (2 GiB HBM budget, 64 replica slots, 2^21 particles) and,
+on the same arrivals, one at a time; per-step latency percentiles come from device time
+stamps written at the end of every step.
 """
 from __future__ import annotations
 
@@ -98,8 +105,13 @@ def cpu_baseline(wl, target_s=15.0):
 
 
 def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True):
+    from paper_2609_07842_amd import tune
     wl = W.headline(f=f, seed=seed)
-    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32")
+    # brick edge and workgroup size from the autotuner's cache when it has this workload
+    layout = tune.lookup(tune.fluid_key(wl.N, 0.5, "fp32")) or {}
+    print(f"[bench] device {tune._device_name()}: tuned layout {layout or 'none (automatic)'}",
+          file=sys.stderr, flush=True)
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32", **layout)
     s.set_state(wl.x, wl.v)
     integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=seed)
     # warmup: relax the random start and reach a steady rebuild rate
@@ -153,6 +165,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (reference for byte counters)")
     args = ap.parse_args()
@@ -210,6 +224,20 @@ def main():
         vals = [v["timesteps_per_s"] for v in sweep.values()]
         sweep["flatness_max_over_min"] = max(vals) / min(vals)
 
+    serving = None
+    if not args.no_serve:
+        from paper_2609_07842_amd import serve
+        main_run.pop("system", None)
+        torch.cuda.empty_cache()
+        res = serve.serving_benchmark(n=args.serve_requests,
+                                      log=lambda m: print(m, file=sys.stderr, flush=True))
+        serving = {"p99_step_latency_ms_batched": res["batched"]["step_latency_ms"]["p99"],
+                   "p50_step_latency_ms_batched": res["batched"]["step_latency_ms"]["p50"],
+                   "p99_step_latency_ms_one_at_a_time": res["one_at_a_time"]["step_latency_ms"]["p99"],
+                   "p50_step_latency_ms_one_at_a_time": res["one_at_a_time"]["step_latency_ms"]["p50"],
+                   "throughput_batched_over_one_at_a_time": res["speedup_throughput"],
+                   **res}
+
     cpu = None if args.no_cpu else cpu_baseline(wl)
 
     line = {
@@ -240,6 +268,7 @@ def main():
         "step_model_GBs": step_bytes * tsps / 1e9,
         "roofline": roofline,
         "f_sweep": sweep,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

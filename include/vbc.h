@@ -215,7 +215,7 @@ vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms /* [VBC_NK] 
  * of free or retired replicas exit at once), so the captured step graphs stay valid as the
  * replica set changes.  The use case is the paper's own way of working: its results are
  * sweeps over many independent state points (valency, temperature, density, well depth;
- * Sections 3, 4 and 6), each a separate simulation. */
+ * Sections 3 to 5), each a separate simulation. */
 
 /* Fixed capacity of a pool. */
 typedef struct {

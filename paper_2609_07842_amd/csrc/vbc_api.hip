@@ -407,7 +407,9 @@ Launch launch_for(const Caps &C, const vbc_options &opt)
     P.nbrick_tot = C.nbrick;
     P.b_lo = 0;
     P.nb_launch = C.nbrick;
-    P.list = 0;
+    // with one replica slot every live brick is in the range and a rebuild is all or
+    // nothing, so the work lists would only add a launch per step
+    P.list = C.nrep > 1 ? 0 : -1;
     P.k_max = opt.k_max;
     P.nchunk = opt.k_max / CHUNK;
     P.block = opt.block;

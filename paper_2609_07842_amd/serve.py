@@ -40,6 +40,8 @@ class ServerConfig:
                                                           kT=1.0, gamma=0.1, seed=2024))
     max_inflight: int = 6            # step launches the host may run ahead of the GPU
     max_active: int = 0              # 0 = no limit beyond the pool; 1 = one at a time
+    brick: int = 0                   # 0 = the tuned choice if cached, else the library's
+    block: int = 0
 
 
 def request_desc(req, skin=0.4):
@@ -66,11 +68,12 @@ def layout_for(cfg: ServerConfig):
     descs = [request_desc(dict(N=int(N), f=1.0, E_a=5.0, rho=cfg.rho_max, seed=0), cfg.skin)
              for N in grid]
     for d in descs:
-        fp = _vbc.footprint(d, cfg.precision)
+        fp = _vbc.footprint(d, cfg.precision, brick=cfg.brick)
         k_max, stage_cap = max(k_max, fp["k_max"]), max(stage_cap, fp["stage_cap"])
         bcap_max, bcap_min = max(bcap_max, fp["bcap"]), min(bcap_min, fp["bcap"])
     per_slot = min(fp["bytes"] / fp["slots"] for fp in
-                   (_vbc.footprint(d, cfg.precision, k_max=k_max, stage_cap=stage_cap) for d in descs))
+                   (_vbc.footprint(d, cfg.precision, k_max=k_max, stage_cap=stage_cap, brick=cfg.brick)
+                    for d in descs))
     return dict(k_max=k_max, stage_cap=stage_cap, bcap_max=bcap_max, bcap_min=bcap_min,
                 bytes_per_slot=per_slot)
 
@@ -82,6 +85,11 @@ class Server:
         self.torch = torch
         self.cfg = cfg or ServerConfig()
         c = self.cfg
+        if not c.brick and not c.block:
+            from . import tune
+            best = tune.lookup(tune.pool_key(c))
+            if best:
+                c.brick, c.block = best["brick"], best["block"]
         lay = layout_for(c)
         self.k_max, self.stage_cap = lay["k_max"], lay["stage_cap"]
         # capacities that the byte budget reaches first: a replica's slots cost at least
@@ -92,7 +100,7 @@ class Server:
                     max_slots=max(max_slots, c.max_particles), max_bricks=max_bricks,
                     max_cells=max_bricks * 64, max_bcap=max(lay["bcap_max"], 64), chains=False)
         self.pool = _vbc.Pool(caps, precision=c.precision, k_max=self.k_max,
-                              stage_cap=self.stage_cap, device=device)
+                              stage_cap=self.stage_cap, brick=c.brick, block=c.block, device=device)
         self.device = self.pool.device
         self.stream = torch.cuda.current_stream(self.device)
         self._warm()
@@ -112,7 +120,7 @@ class Server:
 
     def footprint(self, req):
         return _vbc.footprint(request_desc(req, self.cfg.skin), self.cfg.precision,
-                              k_max=self.k_max, stage_cap=self.stage_cap)["bytes"]
+                              k_max=self.k_max, stage_cap=self.stage_cap, brick=self.cfg.brick)["bytes"]
 
     def run(self, requests, arrivals=None, keep_results=False):
         """Serve `requests` (dicts with N, f, E_a, rho, seed, steps and device tensors x, v

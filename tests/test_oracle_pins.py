@@ -239,7 +239,8 @@ def _plain_pair_sum(x, L, p, with_attraction=True):
 
 
 def test_no_vbc_limit_is_bare_softcore():
-    # "No VBC, f = 1000: the cap is never reached" (Section 6.2, item iv)
+    # Section 6.2, item iv: with f = 1000 no count comes near the threshold, so Psi = 1
+    # everywhere and U is the plain soft-core pair sum
     p = W.stability_sets(E_a=4.0)["none"]
     x, L = _rand_system(80, 0.5, seed=21)
     r = oracle.evaluate(x, L, p)
