@@ -110,9 +110,9 @@ typedef struct {
 enum { VBC_NVE = 0, VBC_LANGEVIN = 1 };
 
 /* Integrator.  NVE: velocity Verlet.  LANGEVIN: BAOAB splitting with friction gamma at
- * temperature kT; noise from Philox4x64-10 keyed by (seed + replica seed, tag), counter
- * (step, 0, 0, 0),
- * each of the first three words mapped to sqrt(3) (2u - 1), u = (word >> 11) 2^-53. */
+ * temperature kT; noise from Philox4x32-10 with key = the 32-bit halves of
+ * (seed + replica seed) and counter = the halves of step, then of tag; each of the first
+ * three output words w is mapped to sqrt(3) (2u - 1), u = (w + 1/2) 2^-32. */
 typedef struct {
     int32_t kind;
     double dt, kT, gamma;

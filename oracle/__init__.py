@@ -73,8 +73,8 @@ def lib():
                                        C.c_int64, dp, dp, dp]
         L.vbco_bonds.restype = C.c_double
         L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp]
-        L.vbco_philox4x64_10.restype = None
-        L.vbco_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.vbco_philox4x32_10.restype = None
+        L.vbco_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.vbco_noise.restype = None
         L.vbco_noise.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, dp]
         L.vbco_run.restype = None
@@ -222,11 +222,11 @@ def bonds_energy_forces(x, L, bonds, k, r0):
     return U, F
 
 
-def philox4x64_10(counter, key):
-    c = (C.c_uint64 * 4)(*[int(v) for v in counter])
-    k = (C.c_uint64 * 2)(*[int(v) for v in key])
-    o = (C.c_uint64 * 4)()
-    lib().vbco_philox4x64_10(c, k, o)
+def philox4x32_10(counter, key):
+    c = (C.c_uint32 * 4)(*[int(v) for v in counter])
+    k = (C.c_uint32 * 2)(*[int(v) for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().vbco_philox4x32_10(c, k, o)
     return [int(v) for v in o]
 
 

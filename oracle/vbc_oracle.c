@@ -472,31 +472,31 @@ double vbco_bonds(int64_t N, const double *x, const double *L, const int64_t *bo
 }
 
 /* ------------------------------------------------------------------------- */
-/* Counter-based random numbers: Philox4x64-10                                */
+/* Counter-based random numbers: Philox4x32-10                                */
 /* ------------------------------------------------------------------------- */
 
-/* Philox4x64 with 10 rounds, from its published definition (Salmon, Moraes, Dror &
+/* Philox4x32 with 10 rounds, from its published definition (Salmon, Moraes, Dror &
  * Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11): each round multiplies
- * counter words 0 and 2 by two fixed odd constants, takes the high and low halves of
- * the 128-bit products, mixes the high halves with the other counter words and the
+ * counter words 0 and 2 by two fixed odd 32-bit constants, takes the high and low halves
+ * of the 64-bit products, mixes the high halves with the other counter words and the
  * round key, and bumps the key by two Weyl constants between rounds. */
-void vbco_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+void vbco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
-    uint64_t k0 = key[0], k1 = key[1];
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
     for (int r = 0; r < 10; ++r) {
         if (r > 0) {
             k0 += W0;
             k1 += W1;
         }
-        unsigned __int128 p0 = (unsigned __int128)M0 * c0;
-        unsigned __int128 p1 = (unsigned __int128)M1 * c2;
-        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
-        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
-        uint64_t n0 = hi1 ^ c1 ^ k0;
-        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -509,19 +509,20 @@ void vbco_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t o
 }
 
 /* Langevin noise of one particle for one step.  Reading (the paper states only the
- * friction): key = (seed, tag), counter = (step, 0, 0, 0); each of the first three
- * output words gives a uniform u = (word >> 11) * 2^-53 in [0, 1), turned into a
- * zero-mean, unit-variance variate sqrt(3) (2u - 1).  Only exactly rounded operations
- * are used, so any other implementation of the same steps reproduces it bit for bit. */
+ * friction): key = the two 32-bit halves of seed (low first), counter = the halves of
+ * step, then of tag; each of the first three output words w gives a uniform
+ * u = (w + 1/2) 2^-32 in (0, 1), turned into a zero-mean, unit-variance variate
+ * sqrt(3) (2u - 1).  Only exactly rounded operations are used, so any other
+ * implementation of the same steps reproduces it bit for bit. */
 void vbco_noise(uint64_t seed, uint64_t tag, uint64_t step, double xi[3])
 {
     const double SQRT3 = 1.7320508075688772;
-    uint64_t ctr[4] = {step, 0, 0, 0};
-    uint64_t key[2] = {seed, tag};
-    uint64_t w[4];
-    vbco_philox4x64_10(ctr, key, w);
+    uint32_t ctr[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)tag, (uint32_t)(tag >> 32)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    vbco_philox4x32_10(ctr, key, w);
     for (int a = 0; a < 3; ++a) {
-        double u = (double)(w[a] >> 11) * 0x1.0p-53;
+        double u = ((double)w[a] + 0.5) * 0x1.0p-32;
         xi[a] = (2.0 * u - 1.0) * SQRT3;
     }
 }

@@ -99,24 +99,24 @@ __device__ __forceinline__ Real omega_r(Real x, Real x1, Real x2)
     return q * q;
 }
 
-// Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11): two 64x64->128-bit
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11): two 32x32->64-bit
 // multiplies by fixed odd constants per round, high halves xor-ed with the other two
 // counter words and the round key; the key is bumped by two Weyl constants per round.
-__device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64_t &c2,
-                                              uint64_t &c3, uint64_t k0, uint64_t k1)
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                              uint32_t &c3, uint32_t k0, uint32_t k1)
 {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) {
             k0 += W0;
             k1 += W1;
         }
-        uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
-        uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
-        uint64_t n0 = hi1 ^ c1 ^ k0;
-        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
+        uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -125,17 +125,19 @@ __device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1, uint64
 }
 
 // Zero-mean unit-variance uniform variates sqrt(3)(2u - 1) from the first three words,
-// u = (word >> 11) 2^-53: only exactly rounded operations.
+// u = (word + 1/2) 2^-32; key = the halves of seed, counter = the halves of step, then of
+// tag: only exactly rounded operations.
 __device__ __forceinline__ void langevin_noise(uint64_t seed, uint64_t tag, uint64_t step,
                                                double xi[3])
 {
 #pragma clang fp contract(off)
-    uint64_t c0 = step, c1 = 0, c2 = 0, c3 = 0;
-    philox4x64_10(c0, c1, c2, c3, seed, tag);
+    uint32_t c0 = (uint32_t)step, c1 = (uint32_t)(step >> 32), c2 = (uint32_t)tag,
+             c3 = (uint32_t)(tag >> 32);
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double SQRT3 = 1.7320508075688772;
-    xi[0] = (2.0 * ((double)(c0 >> 11) * 0x1.0p-53) - 1.0) * SQRT3;
-    xi[1] = (2.0 * ((double)(c1 >> 11) * 0x1.0p-53) - 1.0) * SQRT3;
-    xi[2] = (2.0 * ((double)(c2 >> 11) * 0x1.0p-53) - 1.0) * SQRT3;
+    xi[0] = (2.0 * (((double)c0 + 0.5) * 0x1.0p-32) - 1.0) * SQRT3;
+    xi[1] = (2.0 * (((double)c1 + 0.5) * 0x1.0p-32) - 1.0) * SQRT3;
+    xi[2] = (2.0 * (((double)c2 + 0.5) * 0x1.0p-32) - 1.0) * SQRT3;
 }
 
 template <class T>

@@ -6,7 +6,8 @@ hand from the equations of Section 2), the gradient of the energy by finite
 differences, exact invariants (zero net force, virial by box scaling), special
 parameter sets that reduce to plain pair potentials (Section 6.2), the stability
 bound eq. (Hstable), an independent library neighbour search (scipy cKDTree), the
-integer-count property of r_l = r_a (Section 2.1), and numpy's Philox generator.
+integer-count property of r_l = r_a (Section 2.1), and the published known-answer
+vectors of the Philox4x32-10 generator.
 """
 import json
 import math
@@ -371,41 +372,52 @@ def test_neighbor_pairs_match_kdtree(N, rho, rc):
 
 
 # ---------------------------------------------------------------------------
-# Philox4x64-10 and the noise transform
+# Philox4x32-10 and the noise transform
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ctr,key", [
-    ([0, 0, 0, 0], [0, 0]),
-    ([5, 0, 0, 0], [12345, 678]),
-    ([2**64 - 2, 2**64 - 1, 7, 2**63], [2**64 - 1, 3]),
-    ([123456789, 0, 0, 0], [42, 999999]),
-])
-def test_philox_matches_numpy(ctr, key):
-    # numpy's Philox is Philox4x64-10; Philox(counter=c).random_raw() is the block of c + 1
-    c = np.array(ctr, dtype=np.uint64)
-    mine = oracle.philox4x64_10(ctr, key)
-    prev = [int(v) for v in c]
-    # subtract one from the 256-bit counter
-    borrow = 1
-    for w in range(4):
-        t = prev[w] - borrow
-        borrow = 1 if t < 0 else 0
-        prev[w] = t % 2**64
-    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(prev, dtype=np.uint64))
-    assert mine == [int(v) for v in g.random_raw(4)]
+def _kat():
+    rows = []
+    with open(os.path.join(os.path.dirname(GOLDEN), "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                w = [int(t, 16) for t in line.split()]
+                rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+@pytest.mark.parametrize("ctr,key,out", _kat())
+def test_philox_known_answers(ctr, key, out):
+    assert oracle.philox4x32_10(ctr, key) == out
+
+
+def test_philox_counter_and_key_both_matter():
+    base = oracle.philox4x32_10([1, 2, 3, 4], [5, 6])
+    for k in range(4):
+        c = [1, 2, 3, 4]
+        c[k] ^= 1
+        assert oracle.philox4x32_10(c, [5, 6]) != base
+    assert oracle.philox4x32_10([1, 2, 3, 4], [5, 7]) != base
+    assert oracle.philox4x32_10([1, 2, 3, 4], [4, 6]) != base
 
 
 def test_noise_transform_and_moments():
-    seed, tag, step = 77, 12, 345
-    w = oracle.philox4x64_10([step, 0, 0, 0], [seed, tag])
+    seed, tag, step = 77 + (9 << 32), 12 + (3 << 32), 345 + (5 << 32)
+    w = oracle.philox4x32_10([step & 0xFFFFFFFF, step >> 32, tag & 0xFFFFFFFF, tag >> 32],
+                             [seed & 0xFFFFFFFF, seed >> 32])
     xi = oracle.noise(seed, tag, step)
     for a in range(3):
-        u = (w[a] >> 11) * 2.0 ** -53
+        u = (w[a] + 0.5) * 2.0 ** -32
         assert xi[a] == (2.0 * u - 1.0) * 1.7320508075688772
     samples = np.array([oracle.noise(3, t, s) for t in range(60) for s in range(60)]).ravel()
     assert abs(samples.mean()) < 4 / math.sqrt(samples.size)
     assert abs(samples.var() - 1.0) < 0.06
-    assert np.abs(samples).max() <= math.sqrt(3)
+    assert np.abs(samples).max() < math.sqrt(3)
+    # the three components and successive steps are uncorrelated
+    s3 = samples.reshape(-1, 3)
+    c = np.corrcoef(s3.T)
+    assert np.abs(c - np.eye(3)).max() < 4 / math.sqrt(s3.shape[0])
+    a = np.array([oracle.noise(3, 7, s)[0] for s in range(3000)])
+    assert abs(np.corrcoef(a[:-1], a[1:])[0, 1]) < 4 / math.sqrt(a.size)
 
 
 # ---------------------------------------------------------------------------
