@@ -191,8 +191,10 @@ vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 
 /* Counters kept per replica on the GPU (read with vbc_get_stats, which synchronises s):
  * list builds so far, list entries after the last build (sum over particles), ordered
- * pairs inside the interaction cutoff summed over all count passes, and the number of
- * count passes.  pair_evals / evals is the mean number of pair evaluations per pass. */
+ * pairs inside the interaction cutoff summed over the count passes that sample them
+ * (every pass of vbc_count and vbc_force, and the steps of vbc_step whose index inside
+ * the call is a multiple of 8), and the number of those passes.  pair_evals / evals is
+ * the mean number of pair evaluations per pass. */
 typedef struct {
     uint64_t builds, list_entries, pair_evals, evals;
 } vbc_stats;

@@ -653,7 +653,7 @@ static vbc_status eval_forces(vbc_handle h, const Launch &Q, bool thermo, const 
                               double *d_F, double *d_e, hipStream_t s)
 {
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, Q, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, Q, h->cur, nullptr, 0, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, Q, h->cur, nullptr, 0, true, s); }), "count");
     VBC_TRY(h, timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, Q, h->cur, s); }), "embed");
     VBC_TRY(h, timed(h, VBC_K_FORCE, s, [&] {
                 return launch_force(h->B, Q, h->cur, MODE_EVAL, thermo, st, d_F, d_e, s);
@@ -690,12 +690,15 @@ static vbc_status eval_missing(vbc_handle h, const StepArgs &st, hipStream_t s)
 
 // One step after the opening kick, from position buffer c: list rebuild when due, count,
 // dU/dn, force with the closing kick (MODE_MID: and the opening of the next step), and
-// the step's time stamp when those are on.
-static hipError_t launch_step(vbc_handle h, int c, const StepArgs &st, Mode mode, hipStream_t s)
+// the step's time stamp when those are on.  The pair-evaluation statistic is sampled on
+// the steps with k % STATS_EVERY == 0, k = the step's index inside the call.
+static constexpr int STATS_EVERY = 8;
+static hipError_t launch_step(vbc_handle h, int c, const StepArgs &st, Mode mode, int k, hipStream_t s)
 {
+    const bool stats = k % STATS_EVERY == 0;
     hipError_t e = timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, c, s); });
     if (e == hipSuccess)
-        e = timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, c, nullptr, 1, s); });
+        e = timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, c, nullptr, 1, stats, s); });
     if (e == hipSuccess) e = timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, c, s); });
     if (e == hipSuccess)
         e = timed(h, VBC_K_FORCE, s, [&] {
@@ -739,17 +742,17 @@ static hipError_t get_graph(vbc_handle h, int kind, int nsteps, int c, const Ste
     int cc = c;
     if (kind == 0) {
         for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k) {
-            le = launch_step(h, cc, st, MODE_MID, h->cap_stream);
+            le = launch_step(h, cc, st, MODE_MID, k, h->cap_stream);
             cc ^= 1;
         }
     } else {
         le = launch_kick(h, cc, st, h->cap_stream);
         cc ^= 1;
         for (int k = 1; k < nsteps && le == hipSuccess; ++k) {
-            le = launch_step(h, cc, st, MODE_MID, h->cap_stream);
+            le = launch_step(h, cc, st, MODE_MID, k - 1, h->cap_stream);
             cc ^= 1;
         }
-        if (le == hipSuccess) le = launch_step(h, cc, st, MODE_LAST, h->cap_stream);
+        if (le == hipSuccess) le = launch_step(h, cc, st, MODE_LAST, nsteps - 1, h->cap_stream);
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->cap_stream, &g);
@@ -1076,7 +1079,7 @@ vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
     VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
-    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, 0, s); }), "count");
+    VBC_TRY(h, timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, h->cur, d_n, 0, true, s); }), "count");
     return VBC_OK;
 }
 
@@ -1130,18 +1133,19 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
     h->cur ^= 1;
     // nsteps - 1 mid-call steps: whole graphs, then single steps; kernel timing needs the
     // individual launches, so it bypasses the graphs
-    int mid = nsteps - 1;
+    int mid = nsteps - 1, k = 0;
     if (graphs && mid >= GRAPH_STEPS) {
         hipGraphExec_t ge = nullptr;
         VBC_TRY(h, get_graph(h, 0, GRAPH_STEPS, h->cur, st, &ge), "step graph");
-        for (; mid >= GRAPH_STEPS; mid -= GRAPH_STEPS) VBC_TRY(h, hipGraphLaunch(ge, s), "graph launch");
+        for (; mid >= GRAPH_STEPS; mid -= GRAPH_STEPS, k += GRAPH_STEPS)
+            VBC_TRY(h, hipGraphLaunch(ge, s), "graph launch");
     }
-    for (; mid > 0; --mid) {
-        VBC_TRY(h, launch_step(h, h->cur, st, MODE_MID, s), "step");
+    for (; mid > 0; --mid, ++k) {
+        VBC_TRY(h, launch_step(h, h->cur, st, MODE_MID, k, s), "step");
         h->cur ^= 1;
     }
     // last step: closing half-kick only; its forces are kept for the next call
-    VBC_TRY(h, launch_step(h, h->cur, st, MODE_LAST, s), "step");
+    VBC_TRY(h, launch_step(h, h->cur, st, MODE_LAST, k, s), "step");
     return VBC_OK;
 }
 

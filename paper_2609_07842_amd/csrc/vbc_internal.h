@@ -162,7 +162,7 @@ hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, int r, 
                              hipStream_t s);
 hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
-                        hipStream_t s);
+                        bool stats, hipStream_t s);
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s);
 hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, bool thermo,
                         const StepArgs &st, double *F_out, double *e_out, hipStream_t s);

@@ -923,6 +923,9 @@ template <class Real>
 struct PairR {
     Real E_r, c_r, inv_rr2, E_a, c_a, m, inv_w, r_l, inv_dw, c_c, rl2, rh2, rc2;
     Real x1, x2;
+    Real k_r;      // -c_r / r_r^2: V_r'(r)/r = c_r + k_r r^2 inside the core
+    Real nm_w;     // -m / w:  u_a = r / w + nm_w
+    Real nrl_dw;   // -r_l / (r_h - r_l):  u_c = r / (r_h - r_l) + nrl_dw
     int attract;
 };
 
@@ -945,6 +948,9 @@ __device__ __forceinline__ PairR<Real> pair_r(const PairDev &p, double rc2)
     q.rc2 = (Real)rc2;
     q.x1 = (Real)p.x1;
     q.x2 = (Real)p.x2;
+    q.k_r = (Real)(-p.c_r * p.inv_rr2);
+    q.nm_w = (Real)(-p.m * p.inv_w);
+    q.nrl_dw = (Real)(-p.r_l * p.inv_dw);
     q.attract = p.attract;
     return q;
 }
@@ -973,7 +979,9 @@ __device__ __forceinline__ void load_pairs(const RepDev &R, PairR<Real> *pt)
     }
 }
 
-template <class Real, bool MULTI>
+// STATS: also count the ordered pairs inside the interaction cutoff (the pair-evaluation
+// statistic); the step loop samples it on one step in eight.
+template <class Real, bool MULTI, bool STATS>
 __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance)
 {
     using R4 = typename V4<Real>::t;
@@ -1034,7 +1042,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
-            inside += (r2 < p0.rc2) ? 1 : 0;
+            if (STATS) inside += (r2 < p0.rc2) ? 1 : 0;
             Real rr = sqrt_r(r2);
             if (MULTI) {
                 int tj = (int)pj.w;
@@ -1043,9 +1051,9 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
                 Real qq = Real(1) - uu * uu;
                 chunk += ((R.mask[ti] >> tj) & 1u) ? qq * qq : Real(0);
             } else {
-                Real uu = clamp01((rr - p0.r_l) * p0.inv_dw);
-                Real qq = Real(1) - uu * uu;
-                chunk += qq * qq;
+                Real uu = clamp01(fma(rr, p0.inv_dw, p0.nrl_dw));
+                Real qq = fma(-uu, uu, Real(1));
+                chunk = fma(qq, qq, chunk);
             }
             if (++e == CHUNK) {
                 n += (double)chunk;
@@ -1070,14 +1078,16 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         if (n_out) n_out[R.o_off + B.tag[i]] = n;
     }
     if (win) any_win = 1;
-    evals = wave_sum(evals);
-    if ((threadIdx.x % VBC_WAVE) == 0 && evals) atomicAdd(&ev_sum, evals);
+    if (STATS) {
+        evals = wave_sum(evals);
+        if ((threadIdx.x % VBC_WAVE) == 0 && evals) atomicAdd(&ev_sum, evals);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         B.win[b] = (uint8_t)any_win;
-        B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
+        if (STATS) B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
         if (lb == 0) {
-            B.stats[4 * r + 3] += 1ull;
+            if (STATS) B.stats[4 * r + 3] += 1ull;
             // in a time step the count pass opens the step: the step counter (the noise
             // counter of the Langevin O-step that the following force pass starts) advances
             if (advance) B.step[r] += 1ull;
@@ -1240,9 +1250,12 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         return;
     }
     const double *X = B.x[cur];
+    const Real cc0 = pt[0].c_c;
     stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
         spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
-        ssa[t] = sA[src];
+        R2 sa = sA[src];
+        if (!MULTI) sa.y *= cc0;  // one type: the chain-rule term needs only c_c A
+        ssa[t] = sa;
     });
     if (threadIdx.x == 0) {
         spos[P.stage_cap] = dummy_pos<R4>();
@@ -1260,6 +1273,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         R4 pi = spos[t];
         R2 sai = ssa[t];
         int ti = MULTI ? (int)pi.w : 0;
+        const Real cai = p0.c_a * sai.x;
         Real fx = 0, fy = 0, fz = 0, ei = 0;
         Real w0 = 0, wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
@@ -1294,20 +1308,22 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 phr += asum * q.c_c * uc * (Real(1) - uc * uc) * rinv;
             } else {
                 // branch-free: beyond every cutoff (and for the padding slot) all three terms
-                // vanish through the clamps
+                // vanish through the clamps.  phi/r = min(c_r + k_r r^2, 0)
+                //   + [ c_a s_i s_j u_a q_a + (c_c A_i + c_c A_j) u_c (1 - u_c^2) ] / r
                 R2 saj = ssa[u];
                 Real rinv = rsqrt_r(r2 > Real(1e-30) ? r2 : Real(1e-30));
                 Real rr = r2 * rinv;
-                Real tc = fmax(Real(1) - r2 * p0.inv_rr2, Real(0));
-                phr = p0.c_r * tc;
-                ep = p0.E_r * tc * tc;
-                Real uu = (rr - p0.m) * p0.inv_w;
-                Real qq = fmax(Real(1) - uu * uu, Real(0));
-                Real psi = sai.x * saj.x;
-                ep -= p0.E_a * psi * qq * qq;
-                phr += psi * p0.c_a * uu * qq * rinv;
-                Real uc = clamp01((rr - p0.r_l) * p0.inv_dw);
-                phr += (sai.y + saj.y) * p0.c_c * uc * (Real(1) - uc * uc) * rinv;
+                Real pr = fmin(fma(r2, p0.k_r, p0.c_r), Real(0));
+                Real uu = fma(rr, p0.inv_w, p0.nm_w);
+                Real qq = fmax(fma(-uu, uu, Real(1)), Real(0));
+                Real uc = clamp01(fma(rr, p0.inv_dw, p0.nrl_dw));
+                Real g = uc * fma(-uc, uc, Real(1));
+                Real t = fma(sai.y + saj.y, g, cai * saj.x * uu * qq);
+                phr = fma(t, rinv, pr);
+                if (THERMO) {
+                    Real tc = fmax(fma(-r2, p0.inv_rr2, Real(1)), Real(0));
+                    ep = p0.E_r * tc * tc - p0.E_a * (sai.x * saj.x) * qq * qq;
+                }
             }
             fx -= phr * dx;
             fy -= phr * dy;
@@ -1595,18 +1611,26 @@ hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
-                        hipStream_t s)
+template <class Real, bool MULTI>
+static void launch_count_t(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
+                           bool stats, hipStream_t s)
 {
     size_t lds = lds_bytes_count(P);
     unsigned g = brick_grid(P.nb_launch);
+    if (stats) k_count<Real, MULTI, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+    else k_count<Real, MULTI, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+}
+
+hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
+                        bool stats, hipStream_t s)
+{
     bool multi = P.ntypes_max > 1;
     if (P.precision == VBC_FP64) {
-        if (multi) k_count<double, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
-        else k_count<double, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+        if (multi) launch_count_t<double, true>(B, P, cur, n_out, advance, stats, s);
+        else launch_count_t<double, false>(B, P, cur, n_out, advance, stats, s);
     } else {
-        if (multi) k_count<float, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
-        else k_count<float, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+        if (multi) launch_count_t<float, true>(B, P, cur, n_out, advance, stats, s);
+        else launch_count_t<float, false>(B, P, cur, n_out, advance, stats, s);
     }
     return hipGetLastError();
 }
