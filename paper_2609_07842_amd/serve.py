@@ -304,3 +304,29 @@ def serving_benchmark(n=256, steps=1000, seed=5, load=0.8, cfg=None, log=None):
                 saturated=strip(sat), batched=strip(batched), one_at_a_time=strip(single),
                 flagged=len(sat["flagged"]) + len(batched["flagged"]) + len(single["flagged"]),
                 speedup_throughput=batched["particle_steps_per_s"] / single["particle_steps_per_s"])
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="serve the synthetic request stream on one GPU")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--mode", choices=("all", "saturated"), default="all",
+                    help="all: capacity, batched Poisson stream and one at a time; "
+                         "saturated: every request queued at t = 0 only")
+    a = ap.parse_args()
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    if a.mode == "all":
+        res = serving_benchmark(n=a.requests, steps=a.steps, log=say)
+    else:
+        cfg = ServerConfig()
+        reqs = make_requests(n=a.requests, rho=cfg.rho_max, steps=a.steps, n_range=cfg.n_range)
+        res = Server(cfg).run(reqs)
+        res.pop("results", None)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
