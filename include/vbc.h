@@ -189,6 +189,14 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
 /* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
 vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 
+/* Change the knobs that do not touch the workspace layout, for the autotuner: block (the
+ * workgroup size of the brick kernels; 0 = keep).  Results do not change beyond the
+ * rounding of the per-brick energy/virial partial sums (forces and trajectories are
+ * bit-identical).  k_max, brick and stage_cap must be 0 or equal to the current values
+ * (VBC_ERR_UNIMPLEMENTED otherwise: they set the layout); precision must match.  Captured
+ * step graphs are dropped and recaptured on the next vbc_step. */
+vbc_status vbc_tune_set(vbc_handle h, const vbc_options *t);
+
 /* Counters kept per replica on the GPU (read with vbc_get_stats, which synchronises s):
  * list builds so far, list entries after the last build (sum over particles), ordered
  * pairs inside the interaction cutoff summed over the count passes that sample them

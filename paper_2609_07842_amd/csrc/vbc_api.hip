@@ -1024,6 +1024,27 @@ vbc_status vbc_get_options(vbc_handle h, vbc_options *out)
     return VBC_OK;
 }
 
+vbc_status vbc_tune_set(vbc_handle h, const vbc_options *t)
+{
+    if (!h || !t) return fail(VBC_ERR_ARG, "NULL argument");
+    if (t->precision != h->opt.precision) return hfail(h, VBC_ERR_ARG, "precision is fixed at creation");
+    if ((t->k_max && round_up(t->k_max, CHUNK) != h->opt.k_max) || (t->brick && t->brick != h->opt.brick) ||
+        (t->stage_cap && t->stage_cap != h->opt.stage_cap))
+        return hfail(h, VBC_ERR_UNIMPLEMENTED,
+                     "k_max, brick and stage_cap set the workspace layout: make a new handle to change them");
+    if (t->block) {
+        if (t->block < 64 || t->block > 1024 || t->block % 64)
+            return hfail(h, VBC_ERR_ARG, "block must be a multiple of 64 in 64..1024");
+        if (t->block != h->P.block) {
+            h->P.block = t->block;
+            h->opt.block = t->block;
+            for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+            h->graphs.clear();
+        }
+    }
+    return VBC_OK;
+}
+
 vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const double *d_v,
                          const int32_t *d_type, uint64_t step0, hipStream_t s)
 {

@@ -28,7 +28,7 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_get_state", "vbc_build_nlist", "vbc_count", "vbc_force", "vbc_step", "vbc_check",
            "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read",
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
-           "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read")
+           "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -110,6 +110,7 @@ def lib():
             "vbc_retire": [vp, i32, vp],
             "vbc_replica_info": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
             "vbc_stamps": [vp, i32, vp],
+            "vbc_tune_set": [vp, C.POINTER(Options)],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double)],
         }
@@ -249,6 +250,13 @@ class _Handle:
         self._ok(lib().vbc_get_options(self.h, C.byref(o)))
         return dict(precision=o.precision, k_max=o.k_max, brick=o.brick, block=o.block,
                     stage_cap=o.stage_cap)
+
+    def tune_set(self, block=0):
+        """Change the workgroup size of the brick kernels (layout knobs stay as created)."""
+        o = Options()
+        o.precision = self.options()["precision"]
+        o.block = int(block)
+        self._ok(lib().vbc_tune_set(self.h, C.byref(o)))
 
     def _n_of(self, rep):
         raise NotImplementedError

@@ -22,3 +22,32 @@ def test_tune_fluid_small(tmp_path):
     s.step(10, integrator="langevin")
     s.check()
     assert s.options()["block"] == got["block"]
+
+
+def test_tune_set_block_keeps_trajectories_bitwise():
+    """Changing the workgroup size between calls (graphs recaptured) leaves forces and
+    trajectories bit-identical; layout knobs are refused."""
+    import numpy as np
+    from paper_2609_07842_amd import vbc
+    from paper_2609_07842_amd import workloads as W
+    wl = W.fluid(8_000, 0.4, 3.0, seed=5)
+    out = []
+    for switch in (False, True):
+        s = vbc.System(vbc.replica(wl.N, wl.L, wl.params), precision="fp32", block=256)
+        s.set_state(wl.x, wl.v)
+        s.step(40, integrator="langevin", seed=3)
+        if switch:
+            s.tune_set(block=512)
+            assert s.options()["block"] == 512
+        s.step(40, integrator="langevin", seed=3)
+        s.check()
+        x, v = s.get_state()
+        F, _, _ = s.force(energies=False)
+        out.append((x.cpu().numpy(), v.cpu().numpy(), F.cpu().numpy()))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    o = vbc.Options()
+    o.precision = vbc.FP32_MIXED
+    o.brick = 2
+    st = vbc.lib().vbc_tune_set(s.h, o)
+    assert st == vbc.VBC_ERR_UNIMPLEMENTED
