@@ -105,6 +105,9 @@ typedef struct {
     int32_t brick;       /* cells per edge of the cell brick one workgroup owns (1..6) */
     int32_t block;       /* threads per workgroup for brick kernels (64..1024, multiple of 64) */
     int32_t stage_cap;   /* particles staged in LDS per brick (own + halo) */
+    double rho_max;      /* > 0: size slots per brick, staging and k_max so that local
+                            number densities up to rho_max fit anywhere (clustering or phase
+                            separation); 0 = margins around the mean density only */
 } vbc_options;
 
 enum { VBC_NVE = 0, VBC_LANGEVIN = 1 };

@@ -240,6 +240,7 @@ vbc_status check_options(const vbc_options *opt_in, vbc_options &opt)
     if (opt.k_max < 0 || opt.k_max > 65528) return fail(VBC_ERR_ARG, "k_max must be 0..65528");
     if (opt.stage_cap < 0 || opt.stage_cap > 65534)
         return fail(VBC_ERR_ARG, "stage_cap must be 0..65534");
+    if (!(opt.rho_max >= 0.0) || !std::isfinite(opt.rho_max)) return fail(VBC_ERR_ARG, "rho_max must be >= 0");
     if (!opt.brick) opt.brick = brick_default(opt.precision);
     return VBC_OK;
 }
@@ -252,7 +253,7 @@ int stage_cap_for(double rho_cell, int nh)
 
 // Geometry of one replica: cells of edge >= the list radius, bricks of up to brick^3 cells,
 // slots per brick, derived pair constants.
-vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, RepPlan &out)
+vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, double rho_max, RepPlan &out)
 {
     RepDev &R = out.R;
     std::memset(&R, 0, sizeof(R));
@@ -325,6 +326,19 @@ vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, RepPlan &ou
     out.k_mean = (double)d.n / vol * 4.18879020478639 * rl * rl * rl;
     out.k_max_auto = k_max_for(out.k_mean);
     out.stage_cap_auto = stage_cap_for(out.rho_cell, out.nh);
+    if (rho_max > 0.0) {
+        // hold local densities up to rho_max (clustering, phase separation) anywhere
+        const double cell_vol = R.h[0] * R.h[1] * R.h[2];
+        const double own_hold = rho_max * cell_vol * out.ncb;
+        int bc = round_up((int)std::ceil(own_hold * 1.05 + 16.0), 64);
+        R.bcap = (int32_t)std::max<int64_t>(R.bcap, std::min<int64_t>(bc, std::max<int64_t>(64, d.n)));
+        out.slots = (int64_t)R.nbrick * R.bcap;
+        out.stage_cap_auto = std::max(out.stage_cap_auto,
+                                      std::min(65504, round_up((int)std::ceil(rho_max * cell_vol * out.nh * 1.05 + 32.0), 32)));
+        double k_hold = rho_max * 4.18879020478639 * rl * rl * rl;
+        out.k_max_auto = std::max(out.k_max_auto,
+                                  std::min(65528, round_up((int)std::ceil(k_hold * 1.2 + 16.0), CHUNK)));
+    }
     return VBC_OK;
 }
 
@@ -787,7 +801,7 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
     double rho_cell_max = 0.0, k_mean_max = 0.0, own_mean_max = 0.0;
     C.nrep = nrep;
     for (int r = 0; r < nrep; ++r) {
-        st = plan_replica(reps[r], opt.brick, plans[r]);
+        st = plan_replica(reps[r], opt.brick, opt.rho_max, plans[r]);
         if (st != VBC_OK) {
             g_err = "replica " + std::to_string(r) + ": " + g_err;
             return st;
@@ -809,8 +823,13 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
             return fail(VBC_ERR_ARG, "more than 2^31 slots in total");
     }
     if (!opt.block) opt.block = std::max(128, std::min(512, round_up((int)std::ceil(own_mean_max), 64)));
-    opt.k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : k_max_for(k_mean_max);
-    if (!opt.stage_cap) opt.stage_cap = stage_cap_for(rho_cell_max, C.nh_max);
+    int k_auto = k_max_for(k_mean_max), s_auto = stage_cap_for(rho_cell_max, C.nh_max);
+    for (const RepPlan &p : plans) {
+        k_auto = std::max(k_auto, p.k_max_auto);
+        s_auto = std::max(s_auto, p.stage_cap_auto);
+    }
+    opt.k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : k_auto;
+    if (!opt.stage_cap) opt.stage_cap = std::min(65504, s_auto);
     return VBC_OK;
 }
 
@@ -931,7 +950,7 @@ vbc_status vbc_replica_footprint(const vbc_replica_desc *d, const vbc_options *o
     vbc_status st = check_options(opt_in, opt);
     if (st != VBC_OK) return st;
     RepPlan rp;
-    st = plan_replica(*d, opt.brick, rp);
+    st = plan_replica(*d, opt.brick, opt.rho_max, rp);
     if (st != VBC_OK) return st;
     int k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : rp.k_max_auto;
     int stage_cap = opt.stage_cap ? opt.stage_cap : rp.stage_cap_auto;
@@ -952,7 +971,7 @@ vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x,
     if (!h || !d || !d_x || !rep_out) return fail(VBC_ERR_ARG, "NULL argument");
     *rep_out = -1;
     RepPlan rp;
-    vbc_status st = plan_replica(*d, h->opt.brick, rp);
+    vbc_status st = plan_replica(*d, h->opt.brick, h->opt.rho_max, rp);
     if (st != VBC_OK) return hfail(h, st, g_err);
     const RepDev &R = rp.R;
     if (R.ntypes > h->P.ntypes_max) return hfail(h, VBC_ERR_CAPACITY, "more particle types than the pool allows");

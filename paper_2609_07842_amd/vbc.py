@@ -45,7 +45,7 @@ class ReplicaDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("k_max", C.c_int32), ("brick", C.c_int32),
-                ("block", C.c_int32), ("stage_cap", C.c_int32)]
+                ("block", C.c_int32), ("stage_cap", C.c_int32), ("rho_max", C.c_double)]
 
 
 class Integrator(C.Structure):
@@ -182,10 +182,11 @@ def _descs(reps):
     return arr, keep
 
 
-def _options(precision="fp64", k_max=0, brick=0, block=0, stage_cap=0):
+def _options(precision="fp64", k_max=0, brick=0, block=0, stage_cap=0, rho_max=0.0):
     o = Options()
     o.precision = FP64 if precision in ("fp64", FP64) else FP32_MIXED
     o.k_max, o.brick, o.block, o.stage_cap = int(k_max), int(brick), int(block), int(stage_cap)
+    o.rho_max = float(rho_max)
     return o
 
 
@@ -249,7 +250,7 @@ class _Handle:
         o = Options()
         self._ok(lib().vbc_get_options(self.h, C.byref(o)))
         return dict(precision=o.precision, k_max=o.k_max, brick=o.brick, block=o.block,
-                    stage_cap=o.stage_cap)
+                    stage_cap=o.stage_cap, rho_max=o.rho_max)
 
     def tune_set(self, block=0):
         """Change the workgroup size of the brick kernels (layout knobs stay as created)."""
@@ -359,7 +360,7 @@ class System(_Handle):
     """One or more replicas resident on one GPU behind a libvbc handle (vbc_create)."""
 
     def __init__(self, reps, precision="fp64", k_max=0, brick=0, block=0, stage_cap=0,
-                 device="cuda"):
+                 rho_max=0.0, device="cuda"):
         self._init_common(device)
         if isinstance(reps, dict):
             reps = [reps]
@@ -368,7 +369,7 @@ class System(_Handle):
         self.ntot = self.stride = sum(r["n"] for r in reps)
         self.offsets = np.concatenate([[0], np.cumsum([r["n"] for r in reps])]).astype(np.int64)
         arr, keep = _descs(reps)
-        o = _options(precision, k_max, brick, block, stage_cap)
+        o = _options(precision, k_max, brick, block, stage_cap, rho_max)
         n = C.c_size_t(0)
         _check(lib().vbc_workspace_size(arr, self.nrep, C.byref(o), C.byref(n)))
         self._alloc_ws(n.value)

@@ -51,3 +51,17 @@ def test_poisson_arrivals_follow_the_stream_gaps():
     assert np.all(np.diff(t) >= 0)
     assert t[-1] == pytest.approx(sum(q["gap"] for q in reqs) / 50.0)
     assert 256 / t[-1] == pytest.approx(50.0, rel=0.2)
+
+
+def test_rho_max_sizes_the_layout_for_dense_regions():
+    vbc = _lib_or_skip()
+    p = W.vbc_params(f=3.0, E_a=5.0)
+    d = vbc.replica(100_000, W.box_length(100_000, 0.3), p)
+    a = vbc.footprint(d, "fp32")
+    b = vbc.footprint(d, "fp32", rho_max=1.0)
+    assert b["bcap"] > a["bcap"] and b["stage_cap"] > a["stage_cap"] and b["k_max"] > a["k_max"]
+    # a brick of 4^3 cells of edge >= 2.4 at density 1.0 holds ~900 particles: they must fit
+    assert b["bcap"] >= 1.0 * 64 * 2.4 ** 3
+    # at rho_max below the mean density nothing changes
+    c = vbc.footprint(d, "fp32", rho_max=0.1)
+    assert c == a
