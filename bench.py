@@ -2,7 +2,7 @@
 """Benchmark of the VBC hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--f 4] [--no-sweep] [--no-cpu]
-                    [--no-serve] [--serve-requests 256]
+                    [--no-melt] [--no-serve] [--serve-requests 256]
 
 Workload (default): N = 1,000,000 particles, cubic periodic box at number density 0.5,
 uniform random start, standard VBC(1.5, 2.0, 0) on the polynomial soft core (E_r = 20,
@@ -156,6 +156,50 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True):
     return out
 
 
+def run_melt(W, vbc, torch, steps, warmup, seed):
+    """Bead-spring melt: 20,000 chains x 50 beads (N = 10^6) at density 0.85, harmonic
+    bonds k = 100, r0 = 1, every fifth bead a valency-1 sticker (well depth 8) counting only
+    stickers, FP32 pair arithmetic, Langevin kT = 1.  The random-walk start packs beads at
+    bond distance and overlapping chains, so the first `warmup` steps run in a layout sized
+    for local densities up to 2 with a long list (k_max 256); the timed handle is then laid
+    out for the relaxed melt (bricks of 3^3 cells keep the dense staging within LDS)."""
+    wl = W.polymer_melt(seed=seed)
+    integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=seed)
+
+    def make(**opts):
+        return vbc.System(vbc.replica(wl.N, wl.L, wl.params, mask=wl.mask, chain_len=50,
+                                      k_bond=wl.k_bond, r0_bond=wl.r0, skin=W.SKIN),
+                          precision="fp32", brick=3, **opts)
+    s = make(k_max=256, rho_max=2.0)
+    s.set_state(wl.x, wl.v, types=wl.types)
+    s.step(warmup, **integ)
+    s.check()
+    x, v = (t.contiguous() for t in s.get_state())
+    s.close()
+    del s
+    s = make()
+    s.set_state(x, v, types=wl.types)
+    s.step(200, **integ)
+    s.check()
+    st0 = s.stats()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, **integ)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.check()
+    st1 = s.stats()[0]
+    pe = (st1["pair_evals"] - st0["pair_evals"]) / max(st1["evals"] - st0["evals"], 1)
+    tsps = steps / dt
+    return {"workload": "20,000 chains x 50 beads, density 0.85, bonds k=100 r0=1, stickers every "
+                        "5th bead (f=1, eps=8kT, count stickers only), FP32 pair / FP64 integration, "
+                        "Langevin kT=1 gamma=0.1 dt=0.005",
+            "N": wl.N, "steps": steps, "timesteps_per_s": tsps, "pair_evals_per_s": tsps * pe,
+            "pair_evals_per_step": pe, "list_entries_per_particle": st1["list_entries"] / wl.N,
+            "steps_per_rebuild": steps / max(st1["builds"] - st0["builds"], 1),
+            "layout": s.options()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +210,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (reference for byte counters)")
@@ -224,6 +269,12 @@ def main():
         vals = [v["timesteps_per_s"] for v in sweep.values()]
         sweep["flatness_max_over_min"] = max(vals) / min(vals)
 
+    melt = None
+    if not args.no_melt:
+        print("[bench] polymer melt", file=sys.stderr, flush=True)
+        melt = run_melt(W, vbc, torch, steps=1000, warmup=1000, seed=4)
+        torch.cuda.empty_cache()
+
     serving = None
     if not args.no_serve:
         from paper_2609_07842_amd import serve
@@ -268,6 +319,7 @@ def main():
         "step_model_GBs": step_bytes * tsps / 1e9,
         "roofline": roofline,
         "f_sweep": sweep,
+        "polymer_melt": melt,
         "serving": serving,
         "cpu_baseline": cpu,
     }
