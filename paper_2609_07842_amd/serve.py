@@ -151,6 +151,7 @@ class Server:
         done_tick = np.zeros(n_req, dtype=np.int64)
         results = [None] * n_req
         flagged = []
+        busy_steps = set()              # first step of a tick preceded by admissions or a sync
 
         def drain_stamps():
             stamps.append(pool.stamps_read())
@@ -183,6 +184,7 @@ class Server:
                 queue.popleft()
                 active[r] = [k, q["steps"] // S, gstep]
                 admit_t[k] = time.perf_counter() - t0
+                busy_steps.add(gstep)
                 first_step[k] = gstep
                 used_bytes += fps[k]
                 used_particles += q["N"]
@@ -202,6 +204,7 @@ class Server:
                 if a[1] == 0:
                     finished.append(r)
             if finished:
+                busy_steps.add(gstep)
                 st, flags = pool.check(raise_on_error=False)
                 for r in finished:
                     k = active[r][0]
@@ -228,11 +231,18 @@ class Server:
         if len(st) != gstep:
             raise RuntimeError(f"expected {gstep} step stamps, got {len(st)}")
         # per-step latency: interval between a request's successive step completions
-        lat = []
+        lat, quiet = [], []
+        busy = np.zeros(len(st) + 1, dtype=bool)
+        for g in busy_steps:
+            if g < busy.size:
+                busy[g] = True
         for k, q in enumerate(requests):
             g0 = first_step[k]
-            lat.append(np.diff(st[g0:g0 + q["steps"]]))
+            d = np.diff(st[g0:g0 + q["steps"]])
+            lat.append(d)
+            quiet.append(d[~busy[g0 + 1:g0 + q["steps"]]])  # interval ending at step g0 + 1 + m
         lat = np.concatenate(lat) if lat else np.zeros(0)
+        quiet = np.concatenate(quiet) if quiet else np.zeros(0)
         done = t_tick[done_tick]
         req_lat = done - arr
         makespan = float(done.max())
@@ -246,6 +256,11 @@ class Server:
             step_latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
                                  p99=1e3 * float(np.percentile(lat, 99)),
                                  mean=1e3 * float(lat.mean()), n=int(lat.size)),
+            # the same over the steps whose tick did not start with admissions or a host sync
+            step_latency_ms_between_events=dict(
+                p50=1e3 * float(np.percentile(quiet, 50)) if quiet.size else None,
+                p99=1e3 * float(np.percentile(quiet, 99)) if quiet.size else None,
+                n=int(quiet.size)),
             request_latency_s=dict(p50=float(np.percentile(req_lat, 50)),
                                    p99=float(np.percentile(req_lat, 99)),
                                    max=float(req_lat.max())),
