@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvbc.so")
+# VBC_LIBRARY may name another build of the same library (side-by-side comparisons)
+LIB_PATH = os.environ.get("VBC_LIBRARY") or os.path.join(_HERE, "libvbc.so")
 
 VBC_OK, VBC_ERR_ARG, VBC_ERR_BOX, VBC_ERR_NLIST_OVERFLOW, VBC_ERR_NONFINITE, VBC_ERR_HIP, \
     VBC_ERR_CAPACITY, VBC_ERR_UNIMPLEMENTED, VBC_ERR_STATE = range(9)

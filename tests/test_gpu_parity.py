@@ -59,6 +59,9 @@ CASES = [
     ("delta_f3", 1500, W.box_length(1500, 0.15), W.vbc_params(E_a=6.0, f=3.0, delta=0.3)),
     ("exchange_tuned_f2", 1500, W.box_length(1500, 0.12), W.exchange_tuned(E_a=4.0, f=2.0)),
     ("three_cells", 117, 7.3, W.vbc_params(E_a=5.0, f=2.0)),
+    # counts near 10-11 at this density: many particles per brick in the switching window,
+    # so the dU/dn pass takes its LDS-staged branch
+    ("window_heavy_f10", 4000, W.box_length(4000, 0.5), W.vbc_params(E_a=5.0, f=10.0)),
 ]
 
 
@@ -103,7 +106,19 @@ def test_fp32_mixed_parity(name, N, L, params):
     err_F = _normwise(F, ref["F"])
     print(f"  fp32 normwise force error {err_F:.2e}", flush=True)
     assert np.abs(n - ref["n"]).max() <= 1e-5
-    assert err_F <= 1e-5
+    tol = 1e-5
+    if name == "window_heavy_f10":
+        # With counts inside the switching window almost everywhere, A_i = dU/dn_i is large
+        # and the forces depend steeply on the counts, hence on positions: the exact forces
+        # themselves move by ~7e-6 (normwise) when every coordinate is perturbed by the
+        # rounding of the FP32 staged positions (half an ulp at |x| < 8, 2.4e-7).  Bound the
+        # FP32 path by twice that sensitivity of the exact problem (and 1e-5 from below).
+        rng = np.random.default_rng(11)
+        xp = x + rng.uniform(-2.4e-7, 2.4e-7, size=x.shape)
+        sens = _normwise(oracle.evaluate(xp, L, params)["F"], ref["F"])
+        print(f"  exact problem's sensitivity to FP32 position rounding {sens:.2e}", flush=True)
+        tol = max(1e-5, 2.0 * sens)
+    assert err_F <= tol
     esc = np.abs(ref["e"]).sum()
     assert abs(UW[0, 0] - ref["U"]) <= 1e-5 * max(1.0, esc)
     assert abs(UW[0, 1] - ref["W"]) <= 1e-5 * max(1.0, np.abs(ref["W"]) + esc)
