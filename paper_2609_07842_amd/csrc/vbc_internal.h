@@ -22,7 +22,6 @@ constexpr int MAXT = 4;          // particle types per replica
 constexpr int MAX_BRICK = 6;     // cells per brick edge
 constexpr int NH_MAX = (MAX_BRICK + 2) * (MAX_BRICK + 2) * (MAX_BRICK + 2);
 constexpr int CHUNK = 8;         // list entries per 16-byte chunk
-constexpr int EMBED_STAGE_MIN = 16;  // window particles per brick above which dU/dn stages LDS
 constexpr int MAX_REPLICAS = 1024;  // replica slots of one handle
 
 // Derived constants of one type pair.  Everything the kernels need is precomputed on

@@ -213,7 +213,7 @@ struct StageTabs {
 
 __device__ __forceinline__ int unpack_w(int w, int a) { return ((w >> (2 * a)) & 3) - 1; }
 
-__host__ __device__ inline size_t align32(size_t b) { return (b + 31) & ~(size_t)31; }
+__device__ __forceinline__ size_t align32(size_t b) { return (b + 31) & ~(size_t)31; }
 
 __device__ __forceinline__ StageTabs carve_tabs(unsigned char *smem, int nh_cap)
 {
@@ -1136,52 +1136,9 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
         if (any) wl[atomicAdd(&nw, 1)] = t;
     }
     __syncthreads();
+    // 2. eight lanes per window particle, one entry of each list chunk per lane; neighbours
+    //    are gathered from global memory through the brick's staging map
     R2 *sA = (R2 *)B.sA;
-    if (!MULTI && nw >= EMBED_STAGE_MIN) {
-        // 2a. many window particles (condensing fluids): stage the brick's neighbourhood
-        //     (brick-local positions and switching factors) in LDS once, then eight lanes per
-        //     window particle sweep its list chunks against it
-        using R4 = typename V4<Real>::t;
-        R4 *spos = (R4 *)(smem + align32((size_t)P.bcap_max * sizeof(int)));
-        Real *ss = (Real *)(spos + P.stage_cap + 1);
-        const double *X = B.x[cur];
-        stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
-            spos[t] = local_pos<Real>(R, S, X, S_, src, w, 0);
-            ss[t] = sA[src].x;
-        });
-        if (threadIdx.x == 0) {
-            spos[P.stage_cap] = dummy_pos<R4>();
-            ss[P.stage_cap] = Real(0);
-        }
-        __syncthreads();
-        const PairR<Real> p0 = pt[0];
-        const int e = threadIdx.x % CHUNK;
-        const int g = threadIdx.x / CHUNK, ng = blockDim.x / CHUNK;
-        for (int k = g; k < nw; k += ng) {
-            const int t = wl[k];
-            const int64_t i = S.base + t;
-            const R4 pi = spos[t];
-            const int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
-            double acc = 0.0;
-            for (int c = 0; c < nch; ++c) {
-                const uint4 q = B.nl[(size_t)c * S_ + i];
-                const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
-                const int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
-                const R4 pj = spos[u];
-                const Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const Real r2 = dx * dx + dy * dy + dz * dz;
-                const Real uu = fma(sqrt_r(r2), p0.inv_w, p0.nm_w);
-                const Real qq = fmax(fma(-uu, uu, Real(1)), Real(0));  // 0 outside the well
-                acc += (double)(ss[u] * (-p0.E_a * qq * qq));
-            }
-#pragma unroll
-            for (int o = CHUNK / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, CHUNK);
-            if (e == 0) sA[i].y = (Real)(omega_dd64(B.nd[i], R.pair[0].x1, R.pair[0].x2) * acc);
-        }
-        return;
-    }
-    // 2b. few window particles: eight lanes per window particle, one entry of each list
-    //     chunk per lane; neighbours are gathered from global memory through the staging map
     const double *X = B.x[cur];
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
     const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
@@ -1576,11 +1533,7 @@ size_t lds_bytes_count(const Launch &P)
 {
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : 16);
 }
-size_t lds_bytes_embed(const Launch &P)
-{
-    size_t stage = (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 40 : 20);
-    return align32((size_t)P.bcap_max * sizeof(int)) + (P.ntypes_max > 1 ? 0 : stage);
-}
+size_t lds_bytes_embed(const Launch &P) { return (size_t)P.bcap_max * sizeof(int); }
 size_t lds_bytes_force(const Launch &P)
 {
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 48 : 24);
