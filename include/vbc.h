@@ -189,6 +189,17 @@ vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica);
 vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t cap,
                          int64_t *d_count, hipStream_t s);
 
+/* Observables of valency control (Section 3): for every particle the number z_i of
+ * particles within the attraction range r_a of the pair (the paper's instantaneous bond
+ * criterion, r_ij < r_a) and the number p_i within the repulsive core r_r (core
+ * penetrations, Section 6.2), decided in FP64 exactly as the plain definition on the
+ * positions vbc_get_state returns (minimum image by round-half-even, no contraction).
+ * d_z, d_pen: device int32 [Ntot] in caller order, or NULL; d_sums: device int64
+ * [slots][3] = {sum of z_i, number of particles with z_i > f (f of the particle's own type
+ * pair), sum of p_i} per replica, or NULL.  Rebuilds the list first if it is stale. */
+vbc_status vbc_observables(vbc_handle h, int32_t *d_z, int32_t *d_pen, int64_t *d_sums,
+                           hipStream_t s);
+
 /* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
 vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 

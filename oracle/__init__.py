@@ -73,6 +73,8 @@ def lib():
                                        C.c_int64, dp, dp, dp]
         L.vbco_bonds.restype = C.c_double
         L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp]
+        L.vbco_observables.restype = None
+        L.vbco_observables.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, i32p, i32p]
         L.vbco_philox4x32_10.restype = None
         L.vbco_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.vbco_noise.restype = None
@@ -220,6 +222,16 @@ def bonds_energy_forces(x, L, bonds, k, r0):
     U = lib().vbco_bonds(N, _dp(x), _dp(Lv), b.ctypes.data_as(C.POINTER(C.c_int64)),
                          b.shape[0], float(k), float(r0), _dp(F))
     return U, F
+
+
+def observables(x, L, params, types=None):
+    """z_i (neighbours within r_a) and p_i (within r_r) of every particle, int32 arrays."""
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, None)
+    z = np.zeros(N, dtype=np.int32)
+    pen = np.zeros(N, dtype=np.int32)
+    lib().vbco_observables(N, _dp(x), tp, _dp(Lv), nt, tab, z.ctypes.data_as(C.POINTER(C.c_int32)),
+                           pen.ctypes.data_as(C.POINTER(C.c_int32)))
+    return z, pen
 
 
 def philox4x32_10(counter, key):

@@ -472,6 +472,37 @@ double vbco_bonds(int64_t N, const double *x, const double *L, const int64_t *bo
 }
 
 /* ------------------------------------------------------------------------- */
+/* Observables of valency control                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Section 3: two particles count as neighbours when their separation is below the
+ * attraction range, r_ij < r_a (an instantaneous criterion); z_i is the number of such
+ * neighbours of i.  The penetration count p_i of the stability study (Section 6.2) is the
+ * number of particles within the repulsive core, r_ij < r_r.  Both use the radii of the
+ * pair (type_i, type_j) and decide r^2 < r * r in FP64 on the minimum image. */
+void vbco_observables(int64_t N, const double *x, const int32_t *type, const double *L,
+                      int ntypes, const vbco_pair *P, int32_t *z, int32_t *pen)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int ti = type ? type[i] : 0;
+        int32_t zi = 0, pi = 0;
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == i) continue;
+            int tj = type ? type[j] : 0;
+            const vbco_pair *p = &P[ti * ntypes + tj];
+            double d[3];
+            min_image(&x[3 * i], &x[3 * j], L, d);
+            double r2 = norm2(d);
+            if (r2 < p->r_a * p->r_a) ++zi;
+            if (r2 < p->r_r * p->r_r) ++pi;
+        }
+        z[i] = zi;
+        pen[i] = pi;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Counter-based random numbers: Philox4x32-10                                */
 /* ------------------------------------------------------------------------- */
 

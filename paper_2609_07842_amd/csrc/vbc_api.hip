@@ -213,6 +213,7 @@ PairDev derive(const vbc_pair_params &p)
     q.c_a = 4.0 * p.E_a / w;
     q.inv_dw = 1.0 / (p.r_h - p.r_l);
     q.c_c = -4.0 / (p.r_h - p.r_l);
+    q.f = p.f;
     q.attract = p.E_a > 0.0;
     return q;
 }
@@ -1234,6 +1235,16 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
     VBC_TRY(h, launch_rebuild(h->B, restrict_to(h->P, h->reps[rep]), h->cur, s), "rebuild");
     VBC_TRY(h, launch_export_nlist(h->B, h->P, rep, h->reps[rep].nbrick, d_pairs, cap, d_count, s),
             "export");
+    return VBC_OK;
+}
+
+vbc_status vbc_observables(vbc_handle h, int32_t *d_z, int32_t *d_pen, int64_t *d_sums, hipStream_t s)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    VBC_NEED_STATE(h);
+    VBC_LAYOUT(h, s);
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    VBC_TRY(h, launch_observe(h->B, h->P, h->cur, d_z, d_pen, d_sums, s), "observables");
     return VBC_OK;
 }
 

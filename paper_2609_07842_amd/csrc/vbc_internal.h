@@ -36,6 +36,7 @@ struct PairDev {
     double c_a;            // 4 E_a / w   (V_a'(r) = c_a u (1 - u^2))
     double inv_dw;         // 1 / (r_h - r_l)
     double c_c;            // -4 / (r_h - r_l)  (c'(r) = c_c u (1 - u^2))
+    double f;              // valency
     int32_t attract;       // E_a > 0
     int32_t pad;
 };
@@ -171,6 +172,8 @@ hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const S
                              hipStream_t s);
 hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int nbrick,
                                int32_t *pairs, int64_t cap, int64_t *count, hipStream_t s);
+hipError_t launch_observe(const Buffers &B, const Launch &P, int cur, int32_t *z_out,
+                          int32_t *pen_out, int64_t *sums, hipStream_t s);
 size_t lds_bytes_sort(const Launch &P);
 size_t lds_bytes_nlist(const Launch &P);
 size_t lds_bytes_count(const Launch &P);

@@ -1509,6 +1509,79 @@ __global__ void k_export_nlist(Buffers B, Launch P, int rep, int32_t *__restrict
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+__global__ void k_zero_i64(int64_t *p, int n)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0;
+}
+
+// Observables of valency control: for every own particle the number of list neighbours
+// within the attraction range and within the repulsive core of the pair, decided in FP64
+// on the wrapped positions exactly as the plain definition (t = x_i - x_j,
+// d = t - L rint(t / L), r^2 = (dx dx + dy dy) + dz dz, r^2 < r * r), plus per-replica sums
+// {sum z, #(z > f), sum p}.  The list holds every pair within the interaction cutoff.
+__global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_out,
+                          int32_t *__restrict__ pen_out, int64_t *__restrict__ sums)
+{
+    __shared__ StageHdr S;
+    __shared__ unsigned long long tot[3];
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        tot[0] = tot[1] = tot[2] = 0ull;
+    }
+    __syncthreads();
+    if (S.overflow) return;
+    const int64_t S_ = P.nslots;
+    const double *X = B.x[cur];
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    unsigned long long zs = 0, over = 0, ps = 0;
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        const int ti = B.type[i];
+        double wi[3];
+        for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[a * S_ + i], R.L[a]);
+        int z = 0, p = 0;
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            if (u == P.stage_cap) return;  // padding
+            const int64_t j = sm[u];
+            const PairDev &pd = R.pair[ti * MAXT + B.type[j]];
+            double r2;
+            {
+#pragma clang fp contract(off)
+                double d[3];
+                for (int a = 0; a < 3; ++a) {
+                    const double tt = wi[a] - wrap1(X[a * S_ + j], R.L[a]);
+                    d[a] = tt - R.L[a] * rint(tt / R.L[a]);
+                }
+                r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            }
+            z += r2 < pd.ra2 ? 1 : 0;
+            p += r2 < pd.rr2 ? 1 : 0;
+        });
+        const int32_t tg = B.tag[i];
+        if (z_out) z_out[R.o_off + tg] = z;
+        if (pen_out) pen_out[R.o_off + tg] = p;
+        zs += (unsigned long long)z;
+        ps += (unsigned long long)p;
+        over += ((double)z > R.pair[ti * MAXT + ti].f) ? 1ull : 0ull;
+    }
+    zs = wave_sum(zs);
+    over = wave_sum(over);
+    ps = wave_sum(ps);
+    if ((threadIdx.x % VBC_WAVE) == 0) {
+        atomicAdd(&tot[0], zs);
+        atomicAdd(&tot[1], over);
+        atomicAdd(&tot[2], ps);
+    }
+    __syncthreads();
+    if (sums && threadIdx.x < 3)
+        atomicAdd((unsigned long long *)&sums[3 * r + threadIdx.x], tot[threadIdx.x]);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1688,6 +1761,14 @@ hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const S
 {
     if (P.list >= 0) k_worklist<<<1, 1024, 0, s>>>(B, P.nrep);
     k_kick_drift<<<brick_grid(P.nb_launch), 256, 0, s>>>(B, P, cur, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const Buffers &B, const Launch &P, int cur, int32_t *z_out,
+                          int32_t *pen_out, int64_t *sums, hipStream_t s)
+{
+    if (sums) k_zero_i64<<<blocks_for(3 * P.nrep, 256), 256, 0, s>>>(sums, 3 * P.nrep);
+    k_observe<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, cur, z_out, pen_out, sums);
     return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_get_state", "vbc_build_nlist", "vbc_count", "vbc_force", "vbc_step", "vbc_check",
            "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read",
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
-           "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set")
+           "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set",
+           "vbc_observables")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -112,6 +113,7 @@ def lib():
             "vbc_replica_info": [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
             "vbc_stamps": [vp, i32, vp],
             "vbc_tune_set": [vp, C.POINTER(Options)],
+            "vbc_observables": [vp, dp, dp, dp, vp],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double)],
         }
@@ -305,6 +307,16 @@ class _Handle:
         UW = torch.empty((self.nslot, 8), dtype=torch.float64, device=self.device) if energies else None
         self._ok(lib().vbc_force(self.h, _ptr(F), _ptr(e), _ptr(UW), self._stream()))
         return F.t(), e, UW
+
+    def observables(self):
+        """z_i (neighbours within r_a), p_i (within r_r) as int32 tensors in caller order,
+        and per replica {sum z, #(z > f), sum p} as an int64 tensor (slots, 3)."""
+        torch = self.torch
+        z = torch.empty(self.stride, dtype=torch.int32, device=self.device)
+        p = torch.empty(self.stride, dtype=torch.int32, device=self.device)
+        sums = torch.empty((self.nslot, 3), dtype=torch.int64, device=self.device)
+        self._ok(lib().vbc_observables(self.h, _ptr(z), _ptr(p), _ptr(sums), self._stream()))
+        return z, p, sums
 
     def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
         it = Integrator()

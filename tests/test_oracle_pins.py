@@ -480,3 +480,32 @@ def test_bond_forces_gradient():
             g = (oracle.bonds_energy_forces(xp, 20.0, bonds, 100.0, 1.0)[0]
                  - oracle.bonds_energy_forces(xm, 20.0, bonds, 100.0, 1.0)[0]) / (2 * h)
             assert abs(F[i, a] + g) < 1e-5 * max(1.0, np.abs(F).max())
+
+
+# ---------------------------------------------------------------------------
+# observables of valency control (Section 3) and core penetrations (Section 6.2)
+# ---------------------------------------------------------------------------
+
+def test_observables_equal_brute_force_counts():
+    rng = np.random.default_rng(8)
+    N = 240
+    L = np.array([9.0, 10.5, 8.2])
+    x = rng.uniform(0, 1, size=(N, 3)) * L - L  # some coordinates outside the box
+    types = rng.integers(0, 2, size=N).astype(np.int32)
+    pa = W.vbc_params(f=2.0)
+    pb = dict(W.vbc_params(f=3.0), r_r=0.8, r_a=1.3, r_l=1.3, r_h=1.7)
+    pab = dict(W.vbc_params(f=1.0), r_r=0.9, r_a=1.4, r_l=1.4, r_h=1.8)
+    params = [pa, pab, pab, pb]
+    z, pen = oracle.observables(x, L, params, types)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.rint(d / L)
+    r2 = (d[..., 0] ** 2 + d[..., 1] ** 2) + d[..., 2] ** 2
+    np.fill_diagonal(r2, np.inf)
+    ra = np.array([[pa["r_a"], pab["r_a"]], [pab["r_a"], pb["r_a"]]])[types[:, None], types[None, :]]
+    rr = np.array([[pa["r_r"], pab["r_r"]], [pab["r_r"], pb["r_r"]]])[types[:, None], types[None, :]]
+    assert np.array_equal(z, (r2 < ra * ra).sum(1))
+    assert np.array_equal(pen, (r2 < rr * rr).sum(1))
+    # a dimer inside the well and a third particle just outside r_a
+    x3 = np.array([[1.0, 1.0, 1.0], [2.25, 1.0, 1.0], [3.76, 1.0, 1.0]])
+    z3, p3 = oracle.observables(x3, 20.0, W.vbc_params())
+    assert list(z3) == [1, 1, 0] and list(p3) == [0, 0, 0]
