@@ -94,6 +94,12 @@ typedef struct {
     double k_bond, r0_bond;         /* bond energy k/2 (r - r0)^2 */
     uint64_t seed;                  /* added (mod 2^64) to the integrator's seed to give this
                                        replica's Langevin noise key */
+    int32_t excl_span;              /* with chains: beads of one chain at most excl_span apart
+                                       along it neither count each other nor attract (their
+                                       soft-core repulsion stays); 0 = no exclusions.  With
+                                       stickers every s-th bead, excl_span = s forbids binding
+                                       between stickers adjacent along the backbone
+                                       (Section 6.1).  Needs stage_cap <= 32767. */
 } vbc_replica_desc;
 
 /* Layout and launch knobs (0 = automatic).  None of them changes a result beyond the

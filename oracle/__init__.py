@@ -73,6 +73,8 @@ def lib():
                                        C.c_int64, dp, dp, dp]
         L.vbco_bonds.restype = C.c_double
         L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp]
+        L.vbco_set_exclusions.restype = None
+        L.vbco_set_exclusions.argtypes = [C.c_int64, C.c_int64]
         L.vbco_observables.restype = None
         L.vbco_observables.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, i32p, i32p]
         L.vbco_philox4x32_10.restype = None
@@ -181,26 +183,43 @@ def neighbor_pairs(x, L, rc):
         cap = int(n)
 
 
-def counts(x, L, params, types=None, mask=None):
+class _Exclusions:
+    """Chain exclusions for the evaluations inside a with-block (none outside)."""
+
+    def __init__(self, chain_len, excl_span):
+        self.c, self.e = int(chain_len or 0), int(excl_span or 0)
+
+    def __enter__(self):
+        lib().vbco_set_exclusions(self.c, self.e)
+
+    def __exit__(self, *a):
+        lib().vbco_set_exclusions(0, 0)
+
+
+def counts(x, L, params, types=None, mask=None, chain_len=0, excl_span=0):
     x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
     n = np.zeros(N)
-    lib().vbco_counts(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n))
+    with _Exclusions(chain_len, excl_span):
+        lib().vbco_counts(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n))
     return n
 
 
-def evaluate(x, L, params, types=None, mask=None):
-    """Full evaluation.  Returns dict with n, A, F (N x 3), e, U, W, Wt (6)."""
+def evaluate(x, L, params, types=None, mask=None, chain_len=0, excl_span=0):
+    """Full evaluation.  Returns dict with n, A, F (N x 3), e, U, W, Wt (6).  With
+    excl_span > 0, particles of one chain (chain_len consecutive indices) at most excl_span
+    apart neither count each other nor attract."""
     x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
     n = np.zeros(N)
     A = np.zeros(N)
     F = np.zeros((N, 3))
     e = np.zeros(N)
     UW = np.zeros(8)
-    lib().vbco_eval(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n), _dp(A), _dp(F), _dp(e), _dp(UW))
+    with _Exclusions(chain_len, excl_span):
+        lib().vbco_eval(N, _dp(x), tp, _dp(Lv), nt, tab, mp, _dp(n), _dp(A), _dp(F), _dp(e), _dp(UW))
     return {"n": n, "A": A, "F": F, "e": e, "U": UW[0], "W": UW[1], "Wt": UW[2:8].copy()}
 
 
-def evaluate_subset(x, L, params, idx, types=None, mask=None):
+def evaluate_subset(x, L, params, idx, types=None, mask=None, chain_len=0, excl_span=0):
     """n, F (m x 3) and e of the particles idx of a (possibly large) system."""
     x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
@@ -208,8 +227,9 @@ def evaluate_subset(x, L, params, idx, types=None, mask=None):
     n = np.zeros(m)
     F = np.zeros((m, 3))
     e = np.zeros(m)
-    lib().vbco_eval_subset(N, _dp(x), tp, _dp(Lv), nt, tab, mp,
-                           idx.ctypes.data_as(C.POINTER(C.c_int64)), m, _dp(n), _dp(F), _dp(e))
+    with _Exclusions(chain_len, excl_span):
+        lib().vbco_eval_subset(N, _dp(x), tp, _dp(Lv), nt, tab, mp,
+                               idx.ctypes.data_as(C.POINTER(C.c_int64)), m, _dp(n), _dp(F), _dp(e))
     return {"n": n, "F": F, "e": e}
 
 
@@ -252,7 +272,8 @@ NVE, LANGEVIN = 0, 1
 
 
 def run(x, v, L, params, nsteps, kind=NVE, dt=0.005, kT=1.0, gamma=0.1, seed=0, step0=0,
-        types=None, mask=None, tags=None, bonds=None, k_bond=0.0, r0=1.0, history=False):
+        types=None, mask=None, tags=None, bonds=None, k_bond=0.0, r0=1.0, history=False,
+        chain_len=0, excl_span=0):
     """Integrate in place on copies; returns dict x, v, F (+ U, K histories)."""
     x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, mask)
     x = x.copy()
@@ -270,9 +291,10 @@ def run(x, v, L, params, nsteps, kind=NVE, dt=0.005, kT=1.0, gamma=0.1, seed=0, 
     F = np.zeros((N, 3))
     Uh = np.zeros(max(nsteps, 1)) if history else None
     Kh = np.zeros(max(nsteps, 1)) if history else None
-    lib().vbco_run(N, _dp(x), _dp(v), tp, tg, _dp(Lv), nt, tab, mp, bp, nb, float(k_bond),
-                   float(r0), int(kind), float(dt), float(kT), float(gamma), int(seed),
-                   int(step0), int(nsteps), _dp(F), _dp(Uh), _dp(Kh))
+    with _Exclusions(chain_len, excl_span):
+        lib().vbco_run(N, _dp(x), _dp(v), tp, tg, _dp(Lv), nt, tab, mp, bp, nb, float(k_bond),
+                       float(r0), int(kind), float(dt), float(kT), float(gamma), int(seed),
+                       int(step0), int(nsteps), _dp(F), _dp(Uh), _dp(Kh))
     out = {"x": x, "v": v, "F": F}
     if history:
         out["U"] = Uh[:nsteps]

@@ -153,6 +153,28 @@ typedef struct {
     const uint32_t *mask;  /* per type: bit u set => this type counts neighbours of type u */
 } vbco_sys;
 
+/* Chain exclusions (Section 6.1, where binding between stickers adjacent along one
+ * strand is forbidden).  Reading: with chains of chain_len consecutive indices, two
+ * particles of one chain at most excl_span beads apart neither count each other nor
+ * attract; their soft-core repulsion stays.  Applies to every evaluation that follows
+ * until changed; excl_span = 0 switches it off. */
+static int64_t g_chain_len = 0;
+static int64_t g_excl_span = 0;
+
+void vbco_set_exclusions(int64_t chain_len, int64_t excl_span)
+{
+    g_chain_len = chain_len;
+    g_excl_span = excl_span;
+}
+
+static int excluded(int64_t i, int64_t j)
+{
+    if (g_excl_span <= 0 || g_chain_len <= 1) return 0;
+    if (i / g_chain_len != j / g_chain_len) return 0;
+    int64_t d = i - j;
+    return d <= g_excl_span && -d <= g_excl_span;
+}
+
 static int type_of(const vbco_sys *s, int64_t i) { return s->type ? s->type[i] : 0; }
 
 static const vbco_pair *pair_of(const vbco_sys *s, int ti, int tj)
@@ -194,7 +216,7 @@ static double count_one(const vbco_sys *s, int64_t i)
     for (int64_t j = 0; j < s->N; ++j) {
         if (j == i) continue;
         int tj = type_of(s, j);
-        if (!counts_toward(s, ti, tj)) continue;
+        if (!counts_toward(s, ti, tj) || excluded(i, j)) continue;
         const vbco_pair *p = pair_of(s, ti, tj);
         double d[3];
         min_image(&s->x[3 * i], &s->x[3 * j], s->L, d);
@@ -213,7 +235,7 @@ static double embed_one(const vbco_sys *s, const double *n, int64_t i)
     int ti = type_of(s, i);
     double A = 0.0;
     for (int64_t j = 0; j < s->N; ++j) {
-        if (j == i) continue;
+        if (j == i || excluded(i, j)) continue;
         int tj = type_of(s, j);
         const vbco_pair *p = pair_of(s, ti, tj);
         double d[3];
@@ -236,15 +258,16 @@ static void pair_terms(const vbco_sys *s, const double *n, const double *A, int6
     int ti = type_of(s, i), tj = type_of(s, j);
     const vbco_pair *p = pair_of(s, ti, tj);
     double r = sqrt(r2);
-    double psi = switch_s(n[i], p) * switch_s(n[j], p);
+    int ex = excluded(i, j);
+    double psi = ex ? 0.0 : switch_s(n[i], p) * switch_s(n[j], p);
     double e = vbco_Vr(r, p->E_r, p->r_r) + psi * vbco_Va(r, p->E_a, p->r_r, p->r_a);
     double phr = vbco_Vr_d_over_r(r, p->E_r, p->r_r);
     if (r > 0.0) {
         double dva = vbco_Va_d(r, p->E_a, p->r_r, p->r_a);
         double dc = vbco_omega_d(r, p->r_l, p->r_h);
         double chain = 0.0;
-        if (counts_toward(s, ti, tj)) chain += A[i];
-        if (counts_toward(s, tj, ti)) chain += A[j];
+        if (counts_toward(s, ti, tj) && !ex) chain += A[i];
+        if (counts_toward(s, tj, ti) && !ex) chain += A[j];
         phr += (psi * dva + chain * dc) / r;
     }
     (void)d;
@@ -388,7 +411,7 @@ void vbco_eval_subset(int64_t N, const double *x, const int32_t *type, const dou
             int tc = type_of(&s, c);
             double A = 0.0;
             for (int64_t j = 0; j < N; ++j) {
-                if (j == c) continue;
+                if (j == c || excluded(c, j)) continue;
                 int tj = type_of(&s, j);
                 const vbco_pair *p = pair_of(&s, tc, tj);
                 double d[3];
@@ -414,13 +437,14 @@ void vbco_eval_subset(int64_t N, const double *x, const int32_t *type, const dou
             min_image(&x[3 * i], &x[3 * j], L, d);
             double r2 = norm2(d);
             double r = sqrt(r2);
-            double psi = switch_s(n_i, p) * switch_s(nJ[k], p);
+            int ex = excluded(i, j);
+            double psi = ex ? 0.0 : switch_s(n_i, p) * switch_s(nJ[k], p);
             double ep = vbco_Vr(r, p->E_r, p->r_r) + psi * vbco_Va(r, p->E_a, p->r_r, p->r_a);
             double phr = vbco_Vr_d_over_r(r, p->E_r, p->r_r);
             if (r > 0.0) {
                 double chain = 0.0;
-                if (counts_toward(&s, ti, tj)) chain += AJ[nj];
-                if (counts_toward(&s, tj, ti)) chain += AJ[k];
+                if (counts_toward(&s, ti, tj) && !ex) chain += AJ[nj];
+                if (counts_toward(&s, tj, ti) && !ex) chain += AJ[k];
                 phr += (psi * vbco_Va_d(r, p->E_a, p->r_r, p->r_a) +
                         chain * vbco_omega_d(r, p->r_l, p->r_h)) / r;
             }

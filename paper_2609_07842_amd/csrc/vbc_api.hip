@@ -68,7 +68,7 @@ struct RepPlan {
 
 // Fixed capacity of a workspace.
 struct Caps {
-    int32_t nrep = 0, ntypes_max = 1, any_chains = 0, bcap_max = 0, nh_max = 1, ncb_max = 1;
+    int32_t nrep = 0, ntypes_max = 1, any_chains = 0, any_excl = 0, bcap_max = 0, nh_max = 1, ncb_max = 1;
     int64_t ntot = 0, nslots = 0;
     int32_t nbrick = 0, ncell = 0;
 };
@@ -309,6 +309,9 @@ vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, double rho_
         if (d.r0_bond >= 0.5 * std::min(d.L[0], std::min(d.L[1], d.L[2])))
             return fail(VBC_ERR_BOX, "bond length must be below half the box");
     }
+    if (d.excl_span < 0) return fail(VBC_ERR_ARG, "excl_span must be >= 0");
+    if (d.excl_span > 0 && !R.chain_len) return fail(VBC_ERR_ARG, "excl_span needs chains");
+    R.excl_span = R.chain_len ? d.excl_span : 0;
     R.k_bond = d.k_bond;
     R.r0_bond = d.r0_bond;
     R.seed = d.seed;
@@ -434,6 +437,7 @@ Launch launch_for(const Caps &C, const vbc_options &opt)
     P.ncb_max = C.ncb_max;
     P.ntypes_max = C.ntypes_max;
     P.any_chains = C.any_chains;
+    P.multi = (C.ntypes_max > 1 || C.any_excl) ? 1 : 0;
     P.precision = opt.precision;
     return P;
 }
@@ -817,6 +821,7 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
         C.bcap_max = std::max(C.bcap_max, (int)p.R.bcap);
         C.ntypes_max = std::max(C.ntypes_max, (int)p.R.ntypes);
         if (p.R.chain_len) C.any_chains = 1;
+        if (p.R.excl_span) C.any_excl = 1;
         rho_cell_max = std::max(rho_cell_max, p.rho_cell);
         own_mean_max = std::max(own_mean_max, p.own_mean);
         k_mean_max = std::max(k_mean_max, p.k_mean);
@@ -830,7 +835,9 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
         s_auto = std::max(s_auto, p.stage_cap_auto);
     }
     opt.k_max = opt.k_max ? round_up(opt.k_max, CHUNK) : k_auto;
-    if (!opt.stage_cap) opt.stage_cap = std::min(65504, s_auto);
+    if (!opt.stage_cap) opt.stage_cap = std::min(C.any_excl ? 32767 : 65504, s_auto);
+    if (C.any_excl && opt.stage_cap > 32767)
+        return fail(VBC_ERR_ARG, "with chain exclusions stage_cap must be <= 32767");
     return VBC_OK;
 }
 
@@ -898,6 +905,9 @@ static vbc_status check_caps(const vbc_pool_caps *caps, const vbc_options &opt, 
     C.nrep = caps->max_replicas;
     C.ntypes_max = caps->max_types;
     C.any_chains = caps->chains ? 1 : 0;
+    C.any_excl = C.any_chains;  // replicas with chains may carry exclusions
+    if (C.any_excl && opt.stage_cap > 32767)
+        return fail(VBC_ERR_ARG, "a pool with chains needs stage_cap <= 32767");
     C.bcap_max = caps->max_bcap;
     C.nh_max = (opt.brick + 2) * (opt.brick + 2) * (opt.brick + 2);
     C.ncb_max = opt.brick * opt.brick * opt.brick;

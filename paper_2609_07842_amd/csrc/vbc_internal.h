@@ -55,6 +55,8 @@ struct RepDev {
     int32_t nb[3];         // bricks per axis
     int32_t ntypes;
     int32_t chain_len;
+    int32_t excl_span;     // > 0: chain neighbours up to this many beads apart neither count
+                           // nor attract each other (list entries carry bit 15)
     uint32_t mask[MAXT];
     double L[3], h[3];
     double rc2;            // largest interaction cutoff squared
@@ -128,6 +130,7 @@ struct Launch {
     int32_t ncb_max;         // max cells of one brick
     int32_t ntypes_max;
     int32_t any_chains;
+    int32_t multi;           // general pair path: several types or chain exclusions
     int32_t precision;
 };
 

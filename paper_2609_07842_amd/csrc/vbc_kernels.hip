@@ -836,7 +836,16 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
                         }
                         if (in) {
                             int e = nn & (CHUNK - 1);
-                            uint32_t hv = (uint32_t)u << (16 * (e & 1));
+                            uint32_t hv = (uint32_t)u;
+                            if (R.excl_span > 0) {
+                                // chain neighbours up to excl_span beads apart: bit 15
+                                const int ta = B.tags[i], tb = B.tags[ssrc[u]];
+                                const int cl = R.chain_len;
+                                const int db = ta - tb;
+                                if (ta / cl == tb / cl && db <= R.excl_span && -db <= R.excl_span)
+                                    hv |= 0x8000u;
+                            }
+                            hv <<= 16 * (e & 1);
                             if (e < 2) buf[0] |= hv;
                             else if (e < 4) buf[1] |= hv;
                             else if (e < 6) buf[2] |= hv;
@@ -1026,6 +1035,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
+    const bool xr = R.excl_span > 0;  // list entries carry the exclusion bit 15
     bool win = false;
     unsigned long long evals = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -1039,6 +1049,11 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         // omega(r, r_l, r_h) = (1 - u^2)^2 with u = clamp((r - r_l)/(r_h - r_l), 0, 1): exactly 1
         // inside r_l and 0 beyond r_h; partial sums of eight terms are added in FP64
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            int ex = 0;  // pair excluded from counting and attraction (chain neighbours)
+            if (MULTI && xr) {
+                ex = u >> 15;
+                u &= 0x7fff;
+            }
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
@@ -1049,7 +1064,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
                 const PairR<Real> &q = pt[ti * MAXT + tj];
                 Real uu = clamp01((rr - q.r_l) * q.inv_dw);
                 Real qq = Real(1) - uu * uu;
-                chunk += ((R.mask[ti] >> tj) & 1u) ? qq * qq : Real(0);
+                chunk += (((R.mask[ti] >> tj) & 1u) && !ex) ? qq * qq : Real(0);
             } else {
                 Real uu = clamp01(fma(rr, p0.inv_dw, p0.nrl_dw));
                 Real qq = fma(-uu, uu, Real(1));
@@ -1157,6 +1172,9 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
             uint4 q = B.nl[(size_t)c * S_ + i];
             uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
             int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+            if (MULTI && R.excl_span > 0) {
+                if (u & 0x8000) continue;  // excluded pair: no attraction between them
+            }
             if (u == P.stage_cap) continue;  // padding
             int src = sm[u], w = wm[u];
             Real dx = (Real)(xi0 - (X[src] + R.L[0] * (double)unpack_w(w, 0)));
@@ -1264,6 +1282,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
+    const bool xr = R.excl_span > 0;  // list entries carry the exclusion bit 15
     const uint64_t step = B.step[r];
     const uint64_t key = st.seed + R.seed;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
@@ -1277,6 +1296,11 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         Real fx = 0, fy = 0, fz = 0, ei = 0;
         Real w0 = 0, wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            int ex = 0;  // pair excluded from counting and attraction (chain neighbours)
+            if (MULTI && xr) {
+                ex = u >> 15;
+                u &= 0x7fff;
+            }
             R4 pj = spos[u];
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
@@ -1292,7 +1316,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 tc = tc > Real(0) ? tc : Real(0);
                 phr = q.c_r * tc;
                 ep = q.E_r * tc * tc;
-                if (q.attract) {
+                if (q.attract && !ex) {
                     Real uu = (rr - q.m) * q.inv_w;
                     Real qq = Real(1) - uu * uu;
                     if (qq > Real(0)) {
@@ -1301,8 +1325,9 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                         phr += psi * q.c_a * uu * qq * rinv;
                     }
                 }
-                Real asum = (((R.mask[ti] >> tj) & 1u) ? sai.y : Real(0)) +
-                            (((R.mask[tj] >> ti) & 1u) ? saj.y : Real(0));
+                Real asum = ex ? Real(0)
+                               : (((R.mask[ti] >> tj) & 1u) ? sai.y : Real(0)) +
+                                     (((R.mask[tj] >> ti) & 1u) ? saj.y : Real(0));
                 Real uc = (rr - q.r_l) * q.inv_dw;
                 uc = uc < Real(0) ? Real(0) : (uc > Real(1) ? Real(1) : uc);
                 phr += asum * q.c_c * uc * (Real(1) - uc * uc) * rinv;
@@ -1497,6 +1522,7 @@ __global__ void k_export_nlist(Buffers B, Launch P, int rep, int32_t *__restrict
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
         for_each_neighbour(B.nl, P.nslots, i, B.nn[i], [&](int u) {
+            if (R.excl_span > 0) u &= 0x7fff;
             if (u == P.stage_cap) return;  // padding
             unsigned long long k = atomicAdd(count, 1ull);
             if ((int64_t)k < cap) {
@@ -1546,6 +1572,7 @@ __global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_
         for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[a * S_ + i], R.L[a]);
         int z = 0, p = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            if (R.excl_span > 0) u &= 0x7fff;
             if (u == P.stage_cap) return;  // padding
             const int64_t j = sm[u];
             const PairDev &pd = R.pair[ti * MAXT + B.type[j]];
@@ -1697,7 +1724,7 @@ static void launch_count_t(const Buffers &B, const Launch &P, int cur, double *n
 hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
                         bool stats, hipStream_t s)
 {
-    bool multi = P.ntypes_max > 1;
+    bool multi = P.multi != 0;
     if (P.precision == VBC_FP64) {
         if (multi) launch_count_t<double, true>(B, P, cur, n_out, advance, stats, s);
         else launch_count_t<double, false>(B, P, cur, n_out, advance, stats, s);
@@ -1711,7 +1738,7 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
     unsigned g = brick_grid(P.nb_launch);
-    bool multi = P.ntypes_max > 1;
+    bool multi = P.multi != 0;
     const int bs = 256;
     size_t lds = lds_bytes_embed(P);
     if (P.precision == VBC_FP64) {
@@ -1739,7 +1766,7 @@ static void launch_force_t(const Buffers &B, const Launch &P, int cur, Mode mode
 hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, bool thermo,
                         const StepArgs &st, double *F_out, double *e_out, hipStream_t s)
 {
-    bool multi = P.ntypes_max > 1;
+    bool multi = P.multi != 0;
     if (P.precision == VBC_FP64) {
         if (multi) launch_force_t<double, true>(B, P, cur, mode, thermo, st, F_out, e_out, s);
         else launch_force_t<double, false>(B, P, cur, mode, thermo, st, F_out, e_out, s);

@@ -42,7 +42,7 @@ class ReplicaDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("L", C.c_double * 3), ("ntypes", C.c_int32),
                 ("params", C.POINTER(PairParams)), ("count_mask", C.POINTER(C.c_uint32)),
                 ("skin", C.c_double), ("chain_len", C.c_int32), ("k_bond", C.c_double),
-                ("r0_bond", C.c_double), ("seed", C.c_uint64)]
+                ("r0_bond", C.c_double), ("seed", C.c_uint64), ("excl_span", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -149,14 +149,17 @@ def _pair_array(params, ntypes):
     return arr
 
 
-def replica(n, L, params, mask=None, skin=0.4, chain_len=0, k_bond=0.0, r0_bond=1.0, seed=0):
+def replica(n, L, params, mask=None, skin=0.4, chain_len=0, k_bond=0.0, r0_bond=1.0, seed=0,
+            excl_span=0):
     """Description of one replica (host side).  params: dict or list of ntypes^2 dicts;
-    seed is added to the integrator's seed to key this replica's noise."""
+    seed is added to the integrator's seed to key this replica's noise; excl_span > 0
+    (with chains) removes counting and attraction between beads of one chain at most that
+    many beads apart."""
     ntypes = 1 if isinstance(params, dict) else int(round(len(params) ** 0.5))
     return dict(n=int(n), L=np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy(),
                 params=params, ntypes=ntypes, mask=None if mask is None else np.asarray(mask, np.uint32),
                 skin=float(skin), chain_len=int(chain_len), k_bond=float(k_bond), r0_bond=float(r0_bond),
-                seed=int(seed))
+                seed=int(seed), excl_span=int(excl_span))
 
 
 def _descs(reps):
@@ -182,6 +185,7 @@ def _descs(reps):
         d.k_bond = r["k_bond"]
         d.r0_bond = r["r0_bond"]
         d.seed = r.get("seed", 0) & 0xFFFFFFFFFFFFFFFF
+        d.excl_span = int(r.get("excl_span", 0))
     return arr, keep
 
 

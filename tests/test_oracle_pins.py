@@ -509,3 +509,64 @@ def test_observables_equal_brute_force_counts():
     x3 = np.array([[1.0, 1.0, 1.0], [2.25, 1.0, 1.0], [3.76, 1.0, 1.0]])
     z3, p3 = oracle.observables(x3, 20.0, W.vbc_params())
     assert list(z3) == [1, 1, 0] and list(p3) == [0, 0, 0]
+
+
+# ---------------------------------------------------------------------------
+# chain exclusions (Section 6.1: binding between stickers adjacent along a strand)
+# ---------------------------------------------------------------------------
+
+def _excl_grad(x, L, params, types, mask, cl, span, h=1e-6):
+    g = np.zeros_like(x)
+    for i in range(x.shape[0]):
+        for a in range(3):
+            xp = x.copy(); xp[i, a] += h
+            xm = x.copy(); xm[i, a] -= h
+            up = oracle.evaluate(xp, L, params, types, mask, chain_len=cl, excl_span=span)["U"]
+            um = oracle.evaluate(xm, L, params, types, mask, chain_len=cl, excl_span=span)["U"]
+            g[i, a] = (up - um) / (2 * h)
+    return g
+
+
+def _sticker_chains(nchains=4, nbeads=10, seed=3):
+    rng = np.random.default_rng(seed)
+    L = 7.0
+    x = []
+    for c in range(nchains):
+        p = rng.uniform(0, L, 3)
+        for b in range(nbeads):
+            x.append(p.copy())
+            p = p + rng.normal(size=3) * 0.6
+    x = np.array(x)
+    types = np.array([1 if b % 2 == 1 else 0 for c in range(nchains) for b in range(nbeads)], np.int32)
+    inert = W.vbc_params(E_a=0.0, f=1.0)
+    sticky = W.vbc_params(E_a=6.0, f=1.0)
+    return x, L, types, [inert, inert, inert, sticky], np.array([0b00, 0b10], np.uint32)
+
+
+def test_exclusions_force_is_minus_gradient_and_change_the_result():
+    x, L, types, params, mask = _sticker_chains()
+    cl, span = 10, 2  # stickers every second bead: neighbouring stickers are 2 apart
+    r = oracle.evaluate(x, L, params, types, mask, chain_len=cl, excl_span=span)
+    r0 = oracle.evaluate(x, L, params, types, mask)
+    assert not np.allclose(r["U"], r0["U"])  # the configuration has excluded sticker contacts
+    g = _excl_grad(x, L, params, types, mask, cl, span)
+    scale = max(1.0, np.abs(r["F"]).max())
+    assert np.abs(r["F"] + g).max() / scale < 2e-6
+    assert np.abs(r["F"].sum(axis=0)).max() <= 1e-12 * scale
+    # subset evaluation agrees with the full one under exclusions
+    idx = np.array([1, 5, 17, 33])
+    rs = oracle.evaluate_subset(x, L, params, idx, types, mask, chain_len=cl, excl_span=span)
+    assert np.abs(rs["F"] - r["F"][idx]).max() <= 1e-12 * scale
+    assert np.abs(rs["n"] - r["n"][idx]).max() <= 1e-12
+
+
+def test_exclusions_of_a_whole_chain_leave_pure_repulsion():
+    # one chain, every pair within it excluded: only the soft core remains, which is the
+    # evaluation with the attraction switched off (E_a = 0) and no counting partners
+    x, L, types, params, mask = _sticker_chains(nchains=1, nbeads=12, seed=9)
+    r = oracle.evaluate(x, L, params, types, mask, chain_len=12, excl_span=11)
+    rep = [dict(p, E_a=0.0) for p in params]
+    r0 = oracle.evaluate(x, L, rep, types, np.array([0, 0], np.uint32))
+    assert abs(r["U"] - r0["U"]) <= 1e-12 * max(1.0, abs(r0["U"]))
+    assert np.abs(r["F"] - r0["F"]).max() <= 1e-12 * max(1.0, np.abs(r0["F"]).max())
+    assert np.all(r["n"] == 0.0)
