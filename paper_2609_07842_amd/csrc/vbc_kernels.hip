@@ -796,10 +796,13 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
     const double rl2 = R.rlist2;
     const float lo2 = (float)(rl2 * (1.0 - 2e-5) - 1e-4), hi2 = (float)(rl2 * (1.0 + 2e-5) + 1e-4);
     const int kmax = P.k_max;
+    // read once: the global descriptor cannot be kept in registers across the list stores
+    const int xspan = R.excl_span, cl = R.chain_len;
     bool ovf = false;
     unsigned long long entries = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
+        const int ta = xspan > 0 ? B.tags[i] : 0;
         int loc = B.lcells[i];
         int lx = loc % S.e[0], ly = (loc / S.e[0]) % S.e[1], lz = loc / (S.e[0] * S.e[1]);
         float4 pi = spos[t];
@@ -837,13 +840,11 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
                         if (in) {
                             int e = nn & (CHUNK - 1);
                             uint32_t hv = (uint32_t)u;
-                            if (R.excl_span > 0) {
+                            if (xspan > 0) {
                                 // chain neighbours up to excl_span beads apart: bit 15
-                                const int ta = B.tags[i], tb = B.tags[ssrc[u]];
-                                const int cl = R.chain_len;
+                                const int tb = B.tags[ssrc[u]];
                                 const int db = ta - tb;
-                                if (ta / cl == tb / cl && db <= R.excl_span && -db <= R.excl_span)
-                                    hv |= 0x8000u;
+                                if (ta / cl == tb / cl && db <= xspan && -db <= xspan) hv |= 0x8000u;
                             }
                             hv <<= 16 * (e & 1);
                             if (e < 2) buf[0] |= hv;
