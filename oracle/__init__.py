@@ -77,6 +77,8 @@ def lib():
         L.vbco_set_exclusions.argtypes = [C.c_int64, C.c_int64]
         L.vbco_observables.restype = None
         L.vbco_observables.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, i32p, i32p]
+        L.vbco_bond_clusters.restype = None
+        L.vbco_bond_clusters.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, i64p, i32p]
         L.vbco_philox4x32_10.restype = None
         L.vbco_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.vbco_noise.restype = None
@@ -252,6 +254,59 @@ def observables(x, L, params, types=None):
     lib().vbco_observables(N, _dp(x), tp, _dp(Lv), nt, tab, z.ctypes.data_as(C.POINTER(C.c_int32)),
                            pen.ctypes.data_as(C.POINTER(C.c_int32)))
     return z, pen
+
+
+def bond_clusters(x, L, params, types=None):
+    """Connected components of the bond graph (r_ij < r_a of the pair, Section 3).
+
+    Returns (label, z): label[i] is the smallest index of i's cluster (int64), z[i] the
+    number of bonds of i (int32)."""
+    x, N, Lv, nt, tab, types, tp, mask, mp = _sys_args(x, L, params, types, None)
+    label = np.zeros(N, dtype=np.int64)
+    z = np.zeros(N, dtype=np.int32)
+    lib().vbco_bond_clusters(N, _dp(x), tp, _dp(Lv), nt, tab, label.ctypes.data_as(C.POINTER(C.c_int64)),
+                             z.ctypes.data_as(C.POINTER(C.c_int32)))
+    return label, z
+
+
+def cluster_stats(label, z, hist_len=0):
+    """Per-cluster sizes s and bond counts e (half the sum of z over the cluster); a cluster is
+    cyclic when it carries a loop, e >= s (a tree has e = s - 1).
+
+    Returns dict: clusters, largest, cyclic_particles (N_cyc), bonds, cyclic_clusters, and,
+    for hist_len > 0, hist[2][hist_len]: row 0 counts all clusters by size, row 1 the acyclic
+    ones; index s < hist_len holds size s, index 0 the clusters of size >= hist_len."""
+    label = np.asarray(label, dtype=np.int64)
+    z = np.asarray(z, dtype=np.int64)
+    roots, inv = np.unique(label, return_inverse=True)
+    size = np.bincount(inv)
+    ends = np.bincount(inv, weights=z).astype(np.int64)
+    assert (ends % 2 == 0).all()
+    edges = ends // 2
+    cyc = edges >= size
+    out = dict(clusters=int(len(roots)), largest=int(size.max()) if len(size) else 0,
+               cyclic_particles=int(size[cyc].sum()), bonds=int(edges.sum()),
+               cyclic_clusters=int(cyc.sum()), sizes=size, edges=edges, roots=roots)
+    if hist_len > 0:
+        h = np.zeros((2, hist_len), dtype=np.int64)
+        b = np.where(size < hist_len, size, 0)
+        np.add.at(h[0], b, 1)
+        np.add.at(h[1], b[~cyc], 1)
+        out["hist"] = h
+    return out
+
+
+def flory_stockmayer(s, f, p, rho):
+    """Number density of tree clusters of size s for valency f and saturation p, eq. (fs):
+    rho w_s (1-p)^f [p (1-p)^(f-2)]^(s-1), w_s = f (fs-s)! / ((fs-2s+2)! s!); the factorials
+    in log form (lgamma)."""
+    from math import lgamma, log, exp
+    s = int(s)
+    lw = log(f) + lgamma(f * s - s + 1) - lgamma(f * s - 2 * s + 3) - lgamma(s + 1)
+    if p <= 0.0:
+        return rho * exp(lw) if s == 1 else 0.0
+    lt = f * log(1.0 - p) + (s - 1) * (log(p) + (f - 2) * log(1.0 - p))
+    return rho * exp(lw + lt)
 
 
 def philox4x32_10(counter, key):

@@ -526,6 +526,42 @@ void vbco_observables(int64_t N, const double *x, const int32_t *type, const dou
     }
 }
 
+/* Clusters of the bond graph (Section 3): i and j are bonded when r_ij < r_a of the pair
+ * (type_i, type_j), the neighbour criterion of z_i above; clusters are the connected
+ * components.  Plain union-find over all pairs i < j, in index order, linking the root with
+ * the larger index under the one with the smaller, so that every particle ends with the
+ * smallest index of its cluster as its label.  z_i (bonds of i) is returned alongside. */
+static int64_t uf_find(int64_t *parent, int64_t a)
+{
+    while (parent[a] != a) a = parent[a];
+    return a;
+}
+
+void vbco_bond_clusters(int64_t N, const double *x, const int32_t *type, const double *L, int ntypes,
+                        const vbco_pair *P, int64_t *label, int32_t *z)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        label[i] = i;
+        z[i] = 0;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        int ti = type ? type[i] : 0;
+        for (int64_t j = i + 1; j < N; ++j) {
+            int tj = type ? type[j] : 0;
+            const vbco_pair *p = &P[ti * ntypes + tj];
+            double d[3];
+            min_image(&x[3 * i], &x[3 * j], L, d);
+            if (!(norm2(d) < p->r_a * p->r_a)) continue;
+            ++z[i];
+            ++z[j];
+            int64_t a = uf_find(label, i), b = uf_find(label, j);
+            if (a < b) label[b] = a;
+            else if (b < a) label[a] = b;
+        }
+    }
+    for (int64_t i = 0; i < N; ++i) label[i] = uf_find(label, i);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Counter-based random numbers: Philox4x32-10                                */
 /* ------------------------------------------------------------------------- */

@@ -570,3 +570,98 @@ def test_exclusions_of_a_whole_chain_leave_pure_repulsion():
     assert abs(r["U"] - r0["U"]) <= 1e-12 * max(1.0, abs(r0["U"]))
     assert np.abs(r["F"] - r0["F"]).max() <= 1e-12 * max(1.0, np.abs(r0["F"]).max())
     assert np.all(r["n"] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# clusters of the bond graph (Section 3) and the Flory-Stockmayer density, eq. (fs)
+# ---------------------------------------------------------------------------
+
+def _shapes_fixture():
+    """Hexagonal ring (side 1.2: neighbours bonded, the next ones at 2.08 are not), a straight
+    chain of four (spacing 1.2), a regular tetrahedron (edge 1.2) and three lone particles,
+    far apart in a 40^3 box, in shuffled order."""
+    pts, kind = [], []
+    for k in range(6):
+        a = 2 * math.pi * k / 6
+        pts.append([5 + 1.2 * math.cos(a), 5 + 1.2 * math.sin(a), 5.0]); kind.append("ring")
+    for k in range(4):
+        pts.append([15 + 1.2 * k, 15.0, 15.0]); kind.append("chain")
+    e = 1.2 / math.sqrt(8.0)
+    for v in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)):
+        pts.append([25 + e * v[0], 25 + e * v[1], 25 + e * v[2]]); kind.append("tetra")
+    for c in ((35, 5, 5), (5, 35, 35), (35, 35, 5)):
+        pts.append(list(map(float, c))); kind.append("lone")
+    order = np.random.default_rng(0).permutation(len(pts))
+    return np.array(pts)[order], [kind[i] for i in order]
+
+
+def test_bond_clusters_of_known_shapes():
+    x, kind = _shapes_fixture()
+    label, z = oracle.bond_clusters(x, 40.0, W.vbc_params())
+    kinds = np.array(kind)
+    # one label per shape, equal to the smallest index of that shape
+    for k in ("ring", "chain", "tetra"):
+        idx = np.flatnonzero(kinds == k)
+        assert (label[idx] == idx.min()).all()
+    for i in np.flatnonzero(kinds == "lone"):
+        assert label[i] == i
+    assert (z[kinds == "ring"] == 2).all() and (z[kinds == "tetra"] == 3).all()
+    assert sorted(z[kinds == "chain"]) == [1, 1, 2, 2] and (z[kinds == "lone"] == 0).all()
+    st = oracle.cluster_stats(label, z, hist_len=8)
+    # ring: s = e = 6 (cyclic); tetrahedron: s = 4, e = 6 (cyclic); chain: tree; lone: trees
+    assert st["clusters"] == 6 and st["largest"] == 6 and st["bonds"] == 6 + 3 + 6
+    assert st["cyclic_clusters"] == 2 and st["cyclic_particles"] == 10
+    assert st["hist"][0].tolist() == [0, 3, 0, 0, 2, 0, 1, 0]
+    assert st["hist"][1].tolist() == [0, 3, 0, 0, 1, 0, 0, 0]
+    # clusters at or above hist_len land in bin 0
+    assert oracle.cluster_stats(label, z, hist_len=5)["hist"][0].tolist() == [1, 3, 0, 0, 2]
+
+
+@pytest.mark.parametrize("rho,f", [(0.05, 2.0), (0.2, 3.0), (0.4, 4.0)])
+def test_bond_clusters_match_library_components(rho, f):
+    """Components against scipy's connected_components on the bond pairs that a k-d tree
+    finds within r_a; bond counts against the z_i of the observables."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    N = 700
+    L = W.box_length(N, rho)
+    x = W.uniform_positions(N, L, 11)
+    params = W.vbc_params(f=f)
+    label, z = oracle.bond_clusters(x, L, params)
+    zr, _ = oracle.observables(x, L, params)
+    assert np.array_equal(z, zr)
+    pairs = cKDTree(np.mod(x, L), boxsize=L).query_pairs(params["r_a"], output_type="ndarray")
+    g = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(N, N))
+    nc, comp = connected_components(g, directed=False)
+    first = np.full(nc, N)
+    np.minimum.at(first, comp, np.arange(N))
+    assert np.array_equal(label, first[comp])
+    st = oracle.cluster_stats(label, z)
+    assert st["clusters"] == nc and st["bonds"] == len(pairs)
+    # a component is cyclic exactly when it has at least as many edges as vertices
+    e = np.bincount(comp[pairs[:, 0]], minlength=nc)
+    s = np.bincount(comp, minlength=nc)
+    assert st["cyclic_clusters"] == int((e >= s).sum())
+
+
+def test_flory_stockmayer_closed_forms():
+    rho = 0.05
+    # w_1 = 1 and w_2 = f / 2 for every valency
+    for f in (2, 3, 4, 6):
+        assert oracle.flory_stockmayer(1, f, 0.3, rho) == pytest.approx(rho * 0.7 ** f, rel=1e-13)
+        assert oracle.flory_stockmayer(2, f, 0.3, rho) == pytest.approx(
+            rho * (f / 2) * 0.7 ** f * 0.3 * 0.7 ** (f - 2), rel=1e-13)
+    # f = 2: linear chains, rho (1 - p)^2 p^(s - 1)
+    for s_ in (1, 3, 10, 40):
+        assert oracle.flory_stockmayer(s_, 2, 0.6, rho) == pytest.approx(rho * 0.4 ** 2 * 0.6 ** (s_ - 1),
+                                                                          rel=1e-12)
+    # below the gel point p_c = 1/(f-1): mass sum_s s rho_s = rho, and the number of tree
+    # clusters sum_s rho_s = rho (1 - f p / 2) (one bond fewer than particles per cluster)
+    for f, p in ((3, 0.3), (4, 0.2), (6, 0.12)):
+        s_ = np.arange(1, 4000)
+        rs = np.array([oracle.flory_stockmayer(k, f, p, rho) for k in s_])
+        assert (s_ * rs).sum() == pytest.approx(rho, rel=1e-9)
+        assert rs.sum() == pytest.approx(rho * (1 - f * p / 2), rel=1e-9)
+    assert oracle.flory_stockmayer(1, 4, 0.0, rho) == pytest.approx(rho, rel=1e-13)
+    assert oracle.flory_stockmayer(2, 4, 0.0, rho) == 0.0
