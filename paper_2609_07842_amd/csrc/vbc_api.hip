@@ -467,6 +467,28 @@ vbc_status hip_fail(vbc_handle h, hipError_t e, const char *where)
         if (_e != hipSuccess) return hip_fail(h, _e, where);     \
     } while (0)
 
+// The largest dynamic LDS request of any kernel at launch shape P must fit the device's
+// per-workgroup limit (with room for the kernels' static LDS).
+static vbc_status check_lds(vbc_handle h, const Launch &P)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
+    int lds_max = 0;
+    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipDeviceGetAttribute");
+    size_t need = std::max(std::max(lds_bytes_nlist(P), lds_bytes_count(P)),
+                           std::max(std::max(lds_bytes_embed(P), lds_bytes_force(P)),
+                                    lds_bytes_sort(P)));
+    if (need + 2048 > (size_t)lds_max) {
+        std::string m = "staging needs " + std::to_string(need) +
+                        " bytes of LDS per workgroup; the device allows " + std::to_string(lds_max) +
+                        " (lower brick, stage_cap or block)";
+        return h ? hfail(h, VBC_ERR_CAPACITY, m) : fail(VBC_ERR_CAPACITY, m);
+    }
+    return VBC_OK;
+}
+
 // Validate the capacity against the device's LDS, make the handle, carve the workspace
 // and clear it (synchronously on s).
 vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d_ws,
@@ -478,19 +500,10 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     if (((uintptr_t)d_ws) & 255) return fail(VBC_ERR_ARG, "workspace must be 256-byte aligned");
     if (ws_bytes < o.bytes)
         return fail(VBC_ERR_CAPACITY, "workspace too small: need " + std::to_string(o.bytes) + " bytes");
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
-    int lds_max = 0;
-    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
-    size_t need = std::max(std::max(lds_bytes_nlist(P), lds_bytes_count(P)),
-                           std::max(std::max(lds_bytes_embed(P), lds_bytes_force(P)),
-                                    lds_bytes_sort(P)));
-    if (need + 2048 > (size_t)lds_max)
-        return fail(VBC_ERR_CAPACITY, "staging needs " + std::to_string(need) +
-                                          " bytes of LDS per workgroup; the device allows " +
-                                          std::to_string(lds_max) + " (lower brick or stage_cap)");
+    {
+        vbc_status st = check_lds(nullptr, P);
+        if (st != VBC_OK) return st;
+    }
 
     vbc_handle h = new (std::nothrow) vbc_handle_s;
     if (!h) return fail(VBC_ERR_ARG, "out of host memory");
@@ -555,7 +568,7 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     B.stamps = at<unsigned long long>(d_ws, o.stamps);
     B.stamp_n = at<unsigned long long>(d_ws, o.stamp_n);
 
-    e = hipHostMalloc((void **)&h->up, sizeof(RepDev) * std::max(C.nrep, 1), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&h->up, sizeof(RepDev) * std::max(C.nrep, 1), hipHostMallocDefault);
     if (e == hipSuccess) {
         h->up_ev.assign(C.nrep, nullptr);
         for (int r = 0; r < C.nrep && e == hipSuccess; ++r)
@@ -1066,6 +1079,10 @@ vbc_status vbc_tune_set(vbc_handle h, const vbc_options *t)
         if (t->block < 64 || t->block > 1024 || t->block % 64)
             return hfail(h, VBC_ERR_ARG, "block must be a multiple of 64 in 64..1024");
         if (t->block != h->P.block) {
+            Launch Q = h->P;
+            Q.block = t->block;
+            vbc_status st = check_lds(h, Q);
+            if (st != VBC_OK) return st;
             h->P.block = t->block;
             h->opt.block = t->block;
             for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
