@@ -104,6 +104,31 @@ def cpu_baseline(wl, target_s=15.0):
             "seconds": dt}
 
 
+def measure_clusters(s, wl, torch, kbar, reps=5):
+    """Cluster analysis of the bond graph on the state the timed steps left: one warm call,
+    then `reps` calls between HIP events on the launch stream.  Algorithmic bytes per
+    particle: the list (2 B per entry + 2 B count), own FP64 position and type, five int32
+    scratch arrays written by the init pass, bonds written and read, the union-find parent
+    read and written twice, the per-root atomics (size, bond ends, smallest tag), and the
+    label pass (parent, smallest tag, tag, label)."""
+    s.clusters(hist_len=4096)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        lab, stats, hist = s.clusters(hist_len=4096)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    st = stats.cpu().numpy()[0]
+    per_particle = 2 * kbar + 2 + 24 + 4 + 5 * 4 + 2 * 4 + 4 * 4 + 3 * 4 + 4 * 4
+    nbytes = per_particle * wl.N
+    return {"ms": ms, "clusters": int(st[0]), "P_inf": float(st[1]) / wl.N, "x_cyc": float(st[2]) / wl.N,
+            "bonds_per_particle": float(st[3]) / wl.N, "bytes_model": nbytes,
+            "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+            "timing": "HIP events around 5 calls of vbc_clusters (scratch init, hooking, counting, "
+                      "labels and histograms) on the launch stream"}
+
+
 def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
     from paper_2609_07842_amd import tune
     wl = W.headline(f=f, seed=seed)
@@ -150,8 +175,9 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
         prof = s.profile_read()
         s.profile(False)
         s.check()
+    clusters = measure_clusters(s, wl, torch, kbar) if profile else None
     out = dict(wl=wl, elapsed=elapsed, pair_evals_per_step=pair_evals, builds=builds, kbar=kbar,
-               prof=prof, elapsed_prof=elapsed_prof, opts=s.options())
+               prof=prof, elapsed_prof=elapsed_prof, opts=s.options(), clusters=clusters)
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -364,6 +390,7 @@ def main():
         "kernels": kernels,
         "step_model_GBs": step_bytes * tsps / 1e9,
         "roofline": roofline,
+        "cluster_analysis": main_run["clusters"],
         "f_sweep": sweep,
         "paper_table_config": paper_table,
         "polymer_melt": melt,

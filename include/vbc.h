@@ -206,6 +206,28 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
 vbc_status vbc_observables(vbc_handle h, int32_t *d_z, int32_t *d_pen, int64_t *d_sums,
                            hipStream_t s);
 
+/* Clusters of the bond graph (Section 3, "Saturation and connectivity", "Cyclisation" and
+ * "Cluster-size distributions"): particles i and j are bonded when r_ij < r_a of the pair,
+ * the criterion of vbc_observables decided the same way; clusters are the connected
+ * components of the bonds within each replica.  A cluster of s particles and e bonds
+ * carries a loop (is cyclic) when e >= s; otherwise it is a tree (e = s - 1).
+ *   d_scratch      device memory of vbc_cluster_scratch_size bytes, 256-byte aligned, owned
+ *                  by the caller; its contents are overwritten (no state is kept)
+ *   d_label        device int32 [Ntot] in caller order, or NULL: the smallest tag (replica-
+ *                  local) of the particle's cluster
+ *   d_stats        device int64 [slots][5] per replica, or NULL: number of clusters, size of
+ *                  the largest (P_inf = largest / N), particles in cyclic clusters (x_cyc =
+ *                  that / N), bonds, cyclic clusters
+ *   d_hist         device int64 [slots][2][hist_len], or NULL: row 0 counts every cluster by
+ *                  size, row 1 the acyclic ones; index s < hist_len holds size s and index 0
+ *                  the clusters of size >= hist_len
+ * Rebuilds the list first if it is stale.  Asynchronous on s; returns VBC_ERR_ARG for a
+ * missing or small scratch, or with d_hist given for hist_len outside 1..2^24 or
+ * 2 x slots x hist_len of 2^31 or more. */
+vbc_status vbc_cluster_scratch_size(vbc_handle h, size_t *bytes);
+vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int32_t *d_label,
+                        int64_t *d_stats, int64_t *d_hist, int32_t hist_len, hipStream_t s);
+
 /* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
 vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 

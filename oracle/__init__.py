@@ -269,6 +269,38 @@ def bond_clusters(x, L, params, types=None):
     return label, z
 
 
+def bond_clusters_large(x, L, params, types=None):
+    """bond_clusters for systems too large for the O(N^2) loop, from library steps: candidate
+    pairs within the largest r_a from a periodic k-d tree (scipy), the exact bond test of the
+    plain definition on each candidate (t = x_i - x_j, d = t - L rint(t / L), r^2 = (dx dx +
+    dy dy) + dz dz < r_a^2 of the pair, numpy elementwise FP64), and scipy's connected
+    components.  Same (label, z) as bond_clusters; positions must lie in [0, L)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    N = len(x)
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    plist = [params] if isinstance(params, dict) else list(params)
+    nt = int(round(len(plist) ** 0.5))
+    ra = np.array([p["r_a"] for p in plist]).reshape(nt, nt)
+    tp = np.zeros(N, dtype=np.int64) if types is None else np.asarray(types, dtype=np.int64)
+    cand = cKDTree(x, boxsize=Lv).query_pairs(float(ra.max()) * (1.0 + 1e-9) + 1e-12, output_type="ndarray")
+    i, j = cand[:, 0], cand[:, 1]
+    t = x[i] - x[j]
+    d = t - Lv * np.rint(t / Lv)
+    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    rr = ra[tp[i], tp[j]]
+    keep = r2 < rr * rr
+    i, j = i[keep], j[keep]
+    z = (np.bincount(i, minlength=N) + np.bincount(j, minlength=N)).astype(np.int32)
+    g = coo_matrix((np.ones(len(i), dtype=np.int8), (i, j)), shape=(N, N))
+    nc, comp = connected_components(g, directed=False)
+    first = np.full(nc, N, dtype=np.int64)
+    np.minimum.at(first, comp, np.arange(N, dtype=np.int64))
+    return first[comp], z
+
+
 def cluster_stats(label, z, hist_len=0):
     """Per-cluster sizes s and bond counts e (half the sum of z over the cluster); a cluster is
     cyclic when it carries a loop, e >= s (a tree has e = s - 1).
@@ -302,6 +334,8 @@ def flory_stockmayer(s, f, p, rho):
     in log form (lgamma)."""
     from math import lgamma, log, exp
     s = int(s)
+    if f * s - 2 * s + 2 < 0:
+        return 0.0  # the reciprocal of a factorial of a negative integer vanishes
     lw = log(f) + lgamma(f * s - s + 1) - lgamma(f * s - 2 * s + 3) - lgamma(s + 1)
     if p <= 0.0:
         return rho * exp(lw) if s == 1 else 0.0

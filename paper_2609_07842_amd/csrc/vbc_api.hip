@@ -479,7 +479,7 @@ static vbc_status check_lds(vbc_handle h, const Launch &P)
     if (e != hipSuccess) return hip_fail(h, e, "hipDeviceGetAttribute");
     size_t need = std::max(std::max(lds_bytes_nlist(P), lds_bytes_count(P)),
                            std::max(std::max(lds_bytes_embed(P), lds_bytes_force(P)),
-                                    lds_bytes_sort(P)));
+                                    std::max(lds_bytes_sort(P), lds_bytes_bonds(P))));
     if (need + 2048 > (size_t)lds_max) {
         std::string m = "staging needs " + std::to_string(need) +
                         " bytes of LDS per workgroup; the device allows " + std::to_string(lds_max) +
@@ -1272,6 +1272,39 @@ vbc_status vbc_observables(vbc_handle h, int32_t *d_z, int32_t *d_pen, int64_t *
     VBC_LAYOUT(h, s);
     VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
     VBC_TRY(h, launch_observe(h->B, h->P, h->cur, d_z, d_pen, d_sums, s), "observables");
+    return VBC_OK;
+}
+
+static size_t cluster_array_bytes(const Launch &P) { return ((size_t)P.nslots * sizeof(int32_t) + 255) & ~(size_t)255; }
+
+vbc_status vbc_cluster_scratch_size(vbc_handle h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(VBC_ERR_ARG, "NULL argument");
+    *bytes = 5 * cluster_array_bytes(h->P);
+    return VBC_OK;
+}
+
+vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int32_t *d_label,
+                        int64_t *d_stats, int64_t *d_hist, int32_t hist_len, hipStream_t s)
+{
+    if (!h || !d_scratch) return fail(VBC_ERR_ARG, "NULL argument");
+    if (scratch_bytes < 5 * cluster_array_bytes(h->P))
+        return hfail(h, VBC_ERR_ARG, "scratch too small: vbc_cluster_scratch_size gives the size");
+    if (((uintptr_t)d_scratch & 255) != 0) return hfail(h, VBC_ERR_ARG, "scratch must be 256-byte aligned");
+    if (d_hist && (hist_len < 1 || hist_len > (1 << 24) || 2 * (int64_t)h->P.nrep * hist_len > INT32_MAX))
+        return hfail(h, VBC_ERR_ARG, "hist_len must be 1..2^24, and 2 x slots x hist_len below 2^31, when d_hist is given");
+    VBC_NEED_STATE(h);
+    VBC_LAYOUT(h, s);
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    const size_t a = cluster_array_bytes(h->P);
+    char *base = (char *)d_scratch;
+    ClusterWork W;
+    W.parent = (int32_t *)(base);
+    W.size = (int32_t *)(base + a);
+    W.ends = (uint32_t *)(base + 2 * a);
+    W.mintag = (int32_t *)(base + 3 * a);
+    W.z = (int32_t *)(base + 4 * a);
+    VBC_TRY(h, launch_clusters(h->B, h->P, h->cur, W, d_label, d_stats, d_hist, d_hist ? hist_len : 0, s), "clusters");
     return VBC_OK;
 }
 

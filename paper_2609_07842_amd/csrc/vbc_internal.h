@@ -177,10 +177,22 @@ hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int n
                                int32_t *pairs, int64_t cap, int64_t *count, hipStream_t s);
 hipError_t launch_observe(const Buffers &B, const Launch &P, int cur, int32_t *z_out,
                           int32_t *pen_out, int64_t *sums, hipStream_t s);
+
+// Scratch of the cluster analysis: five int32 arrays over the slots.
+struct ClusterWork {
+    int32_t *parent;  // union-find forest; after counting, the root of every particle
+    int32_t *size;    // particles per cluster (at the root)
+    uint32_t *ends;   // bond ends per cluster (twice its bonds)
+    int32_t *mintag;  // smallest caller tag per cluster
+    int32_t *z;       // bonds of every particle
+};
+hipError_t launch_clusters(const Buffers &B, const Launch &P, int cur, const ClusterWork &W,
+                           int32_t *label, int64_t *stats, int64_t *hist, int hist_len, hipStream_t s);
 size_t lds_bytes_sort(const Launch &P);
 size_t lds_bytes_nlist(const Launch &P);
 size_t lds_bytes_count(const Launch &P);
 size_t lds_bytes_embed(const Launch &P);
+size_t lds_bytes_bonds(const Launch &P);
 size_t lds_bytes_force(const Launch &P);
 
 }  // namespace vbc

@@ -1547,9 +1547,82 @@ __global__ void k_zero_i64(int64_t *p, int n)
 // on the wrapped positions exactly as the plain definition (t = x_i - x_j,
 // d = t - L rint(t / L), r^2 = (dx dx + dy dy) + dz dz, r^2 < r * r), plus per-replica sums
 // {sum z, #(z > f), sum p}.  The list holds every pair within the interaction cutoff.
+// Squared minimum-image distance from the wrapped position wi of a particle to slot j, in
+// FP64 with the operations of the plain definition (round-half-even image, no contraction):
+// the bond criterion of the observables and of the cluster analysis.
+// Both positions lie in [0, L), so |t| < L and the image index rint(t / L) is -1, 0 or 1;
+// away from |t| = L / 2 the comparison t > L / 2 decides it exactly (the quotient is then
+// far from 1/2), and only that band takes the division.
+__device__ __forceinline__ double obs_r2(const RepDev &R, const double *__restrict__ X, int64_t S_,
+                                         const double wi[3], int64_t j)
+{
+#pragma clang fp contract(off)
+    double d[3];
+    for (int a = 0; a < 3; ++a) {
+        const double La = R.L[a];
+        const double tt = wi[a] - wrap1(X[a * S_ + j], La);
+        const double at = fabs(tt);
+        double k;
+        if (at < 0.375 * La) k = 0.0;
+        else if (at > 0.625 * La) k = tt > 0.0 ? 1.0 : -1.0;
+        else k = rint(tt / La);
+        d[a] = tt - La * k;
+    }
+    return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+// Squared attraction range of the pair (type of own particle i, type of slot j).
+__device__ __forceinline__ double pair_ra2(const RepDev &R, const Buffers &B, int ti, int64_t j)
+{
+    return R.ntypes == 1 ? R.pair[0].ra2 : R.pair[ti * MAXT + B.type[j]].ra2;
+}
+
+// Brick-local FP32 positions (type in w) of every particle the brick staged at the last
+// list build, and the dummy slot far away; optionally their slots.  All threads call this.
+__device__ __forceinline__ void stage_bonds(const Buffers &B, const Launch &P, const RepDev &R,
+                                            const StageHdr &S, int b, const double *X, float4 *spos,
+                                            int32_t *ssrc)
+{
+    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
+        spos[t] = local_pos<float>(R, S, X, P.nslots, src, w, B.type[src]);
+        if (ssrc) ssrc[t] = src;
+    });
+    if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<float4>();
+}
+
+// Threshold r^2 < c2 decided on the staged FP32 distance outside a band around c2 that is
+// wider than the staging's rounding (its error in r^2 stays below 2e-5 for brick-local
+// coordinates), and inside the band by the FP64 expression of the plain definition.
+struct Band {
+    float lo, hi;
+    double c2;
+};
+
+__device__ __forceinline__ Band make_band(double c2)
+{
+    return Band{(float)(c2 * (1.0 - 2e-5) - 1e-4), (float)(c2 * (1.0 + 2e-5) + 1e-4), c2};
+}
+
+__device__ __forceinline__ bool within(float r2f, const Band &bd, const RepDev &R, const double *X,
+                                       int64_t S_, int64_t i, int64_t j)
+{
+    if (r2f < bd.lo) return true;
+    if (!(r2f < bd.hi)) return false;
+    double wi[3];
+    for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[a * S_ + i], R.L[a]);
+    return obs_r2(R, X, S_, wi, j) < bd.c2;
+}
+
+__device__ __forceinline__ float staged_r2(const float4 &a, const float4 &b)
+{
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
 __global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_out,
                           int32_t *__restrict__ pen_out, int64_t *__restrict__ sums)
 {
+    extern __shared__ __align__(16) float4 spos[];  // [stage_cap + 1]
     __shared__ StageHdr S;
     __shared__ unsigned long long tot[3];
     int b, r;
@@ -1565,30 +1638,29 @@ __global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_
     const int64_t S_ = P.nslots;
     const double *X = B.x[cur];
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    stage_bonds(B, P, R, S, b, X, spos, nullptr);
+    __syncthreads();
+    const bool one = R.ntypes == 1;
+    const Band ba0 = make_band(R.pair[0].ra2), br0 = make_band(R.pair[0].rr2);
     unsigned long long zs = 0, over = 0, ps = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         const int64_t i = S.base + t;
-        const int ti = B.type[i];
-        double wi[3];
-        for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[a * S_ + i], R.L[a]);
+        const float4 pi = spos[t];
+        const int ti = (int)pi.w;
         int z = 0, p = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             if (R.excl_span > 0) u &= 0x7fff;
-            if (u == P.stage_cap) return;  // padding
-            const int64_t j = sm[u];
-            const PairDev &pd = R.pair[ti * MAXT + B.type[j]];
-            double r2;
-            {
-#pragma clang fp contract(off)
-                double d[3];
-                for (int a = 0; a < 3; ++a) {
-                    const double tt = wi[a] - wrap1(X[a * S_ + j], R.L[a]);
-                    d[a] = tt - R.L[a] * rint(tt / R.L[a]);
-                }
-                r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            const float4 pj = spos[u];
+            const float r2f = staged_r2(pi, pj);
+            Band ba = ba0, br = br0;
+            if (!one) {
+                const PairDev &pd = R.pair[ti * MAXT + (int)pj.w];
+                ba = make_band(pd.ra2);
+                br = make_band(pd.rr2);
             }
-            z += r2 < pd.ra2 ? 1 : 0;
-            p += r2 < pd.rr2 ? 1 : 0;
+            if (!(r2f < ba.hi) && !(r2f < br.hi)) return;  // beyond both (and the padding)
+            z += within(r2f, ba, R, X, S_, i, sm[u]) ? 1 : 0;
+            p += within(r2f, br, R, X, S_, i, sm[u]) ? 1 : 0;
         });
         const int32_t tg = B.tag[i];
         if (z_out) z_out[R.o_off + tg] = z;
@@ -1606,8 +1678,335 @@ __global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_
         atomicAdd(&tot[2], ps);
     }
     __syncthreads();
-    if (sums && threadIdx.x < 3)
+    if (sums && threadIdx.x < 3 && tot[threadIdx.x])
         atomicAdd((unsigned long long *)&sums[3 * r + threadIdx.x], tot[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// clusters of the bond graph (Section 3): union-find over the slots
+// ---------------------------------------------------------------------------
+//
+// parent[] forms a forest over the slots in which every pointer goes to a smaller slot:
+// hooking links a root under a smaller root, and path halving only ever replaces a parent
+// by one of its ancestors.  Every walk therefore ends, whatever other lanes do meanwhile,
+// and the root of a cluster is its smallest slot.
+
+__device__ __forceinline__ int32_t cc_ld(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void cc_st(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t cc_find(int32_t *parent, int32_t x)
+{
+    while (true) {
+        const int32_t p = cc_ld(parent + x);
+        if (p == x) return x;
+        const int32_t g = cc_ld(parent + p);
+        if (g == p) return p;
+        cc_st(parent + x, g);  // path halving
+        x = g;
+    }
+}
+
+__device__ __forceinline__ void cc_union(int32_t *parent, int32_t a, int32_t b)
+{
+    a = cc_find(parent, a);
+    b = cc_find(parent, b);
+    while (a != b) {
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicCAS(parent + a, a, b);
+        if (old == a) return;
+        a = cc_find(parent, old);
+        b = cc_find(parent, b);
+    }
+}
+
+__global__ void k_cc_init(ClusterWork W, int64_t S_)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S_; i += (int64_t)gridDim.x * blockDim.x) {
+        W.parent[i] = (int32_t)i;
+        W.size[i] = 0;
+        W.ends[i] = 0u;
+        W.mintag[i] = INT32_MAX;
+        W.z[i] = 0;
+    }
+}
+
+// LDS union-find over the own particles of one brick (their staged index is their index in
+// the brick), with the same smaller-root rule.
+__device__ __forceinline__ int32_t lcc_find(int32_t *lp, int32_t x)
+{
+    while (true) {
+        const int32_t p = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == x) return x;
+        const int32_t g = __hip_atomic_load(lp + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (g == p) return p;
+        __hip_atomic_store(lp + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = g;
+    }
+}
+
+__device__ __forceinline__ void lcc_union(int32_t *lp, int32_t a, int32_t b)
+{
+    a = lcc_find(lp, a);
+    b = lcc_find(lp, b);
+    while (a != b) {
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicCAS(lp + a, a, b);
+        if (old == a) return;
+        a = lcc_find(lp, old);
+        b = lcc_find(lp, b);
+    }
+}
+
+// Bonds of every own particle (the z_i criterion of the observables) from its list.  Bonds
+// between two own particles of the brick are joined in LDS first; the forest then starts
+// from the brick's local components, each a star under its smallest slot.
+__global__ void k_cc_local(Buffers B, Launch P, int cur, ClusterWork W)
+{
+    extern __shared__ __align__(16) float4 spos[];  // [stage_cap + 1], then lp[bcap]
+    __shared__ StageHdr S;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) pass_header(R, B, b, lb, P.stage_cap, S);
+    __syncthreads();
+    if (S.overflow) return;
+    const int64_t S_ = P.nslots;
+    const double *X = B.x[cur];
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    int32_t *lp = (int32_t *)(spos + P.stage_cap + 1);
+    stage_bonds(B, P, R, S, b, X, spos, nullptr);
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) lp[t] = t;
+    __syncthreads();
+    const bool one = R.ntypes == 1;
+    const Band ba0 = make_band(R.pair[0].ra2);
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        const float4 pi = spos[t];
+        const int ti = (int)pi.w;
+        int z = 0;
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            if (R.excl_span > 0) u &= 0x7fff;
+            const float4 pj = spos[u];
+            const float r2f = staged_r2(pi, pj);
+            const Band ba = one ? ba0 : make_band(R.pair[ti * MAXT + (int)pj.w].ra2);
+            if (!(r2f < ba.hi)) return;  // also the padding
+            if (!within(r2f, ba, R, X, S_, i, sm[u])) return;
+            ++z;
+            if (u < S.n_own && u > t) lcc_union(lp, t, u);
+        });
+        W.z[i] = z;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x)
+        W.parent[S.base + t] = (int32_t)(S.base + lcc_find(lp, t));
+}
+
+// Bonds that leave the brick join the global forest (each once, from its smaller slot).  A
+// bond is taken between the current parents of its ends (ancestors, so in the same clusters),
+// and a workgroup joins each distinct pair of them once: a condensed brick has hundreds of
+// bonds into a few dozen neighbouring components.  The set of pairs lives in LDS with open
+// addressing; when it is full the join simply runs.
+constexpr int CC_SET = 512;
+
+__global__ void k_cc_hook(Buffers B, Launch P, int cur, ClusterWork W)
+{
+    extern __shared__ __align__(16) float4 spos[];  // [stage_cap + 1], ssrc[stage_cap], set
+    __shared__ StageHdr S;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) pass_header(R, B, b, lb, P.stage_cap, S);
+    __syncthreads();
+    if (S.overflow) return;
+    const int64_t S_ = P.nslots;
+    const double *X = B.x[cur];
+    int32_t *ssrc = (int32_t *)(spos + P.stage_cap + 1);
+    unsigned long long *set =
+        (unsigned long long *)(((uintptr_t)(ssrc + P.stage_cap) + 15) & ~(uintptr_t)15);
+    stage_bonds(B, P, R, S, b, X, spos, ssrc);
+    for (int k = threadIdx.x; k < CC_SET; k += blockDim.x) set[k] = ~0ull;
+    __syncthreads();
+    const bool one = R.ntypes == 1;
+    const Band ba0 = make_band(R.pair[0].ra2);
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        if (W.z[i] == 0) continue;
+        const float4 pi = spos[t];
+        const int ti = (int)pi.w;
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            if (R.excl_span > 0) u &= 0x7fff;
+            if (u < S.n_own || u == P.stage_cap) return;  // inside the brick, or padding
+            const int64_t j = ssrc[u];
+            if (j < i) return;
+            const float4 pj = spos[u];
+            const float r2f = staged_r2(pi, pj);
+            const Band ba = one ? ba0 : make_band(R.pair[ti * MAXT + (int)pj.w].ra2);
+            if (!(r2f < ba.hi) || !within(r2f, ba, R, X, S_, i, j)) return;
+            int32_t pa = cc_ld(W.parent + i), pb = cc_ld(W.parent + j);
+            if (pa == pb) return;
+            if (pa > pb) {
+                const int32_t tmp = pa;
+                pa = pb;
+                pb = tmp;
+            }
+            const unsigned long long key = ((unsigned long long)(uint32_t)pa << 32) | (uint32_t)pb;
+            unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 55) & (CC_SET - 1);
+            for (int probe = 0; probe < 16; ++probe) {
+                const unsigned long long prev = atomicCAS(set + h, ~0ull, key);
+                if (prev == key) return;  // this pair is joined already
+                if (prev == ~0ull) break;  // first of its pair
+                h = (h + 1) & (CC_SET - 1);
+            }
+            cc_union(W.parent, pa, pb);
+        });
+    }
+}
+
+// Size, bond ends and smallest tag of every cluster, gathered at its root; each particle
+// keeps its root as parent for the labelling pass.  A workgroup first sums the particles
+// of the cluster of its first particle in LDS (in a condensed fluid nearly all of them),
+// so that the root of a large cluster takes one atomic per workgroup, not per particle.
+__global__ void k_cc_count(Buffers B, Launch P, ClusterWork W)
+{
+    __shared__ StageHdr S;
+    __shared__ int32_t broot, bmin;
+    __shared__ uint32_t bsize, bends;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        broot = -1;
+        bmin = INT32_MAX;
+        bsize = 0u;
+        bends = 0u;
+    }
+    __syncthreads();
+    if (S.overflow || S.n_own == 0) return;
+    if (threadIdx.x == 0) broot = cc_find(W.parent, (int32_t)S.base);
+    __syncthreads();
+    const int32_t br = broot;
+    uint32_t ls = 0u, le = 0u;
+    int32_t lm = INT32_MAX;
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        const int32_t root = cc_find(W.parent, (int32_t)i);
+        const int32_t tg = B.tag[i];
+        if (root == br) {
+            ls += 1u;
+            le += (uint32_t)W.z[i];
+            lm = tg < lm ? tg : lm;
+        } else {
+            atomicAdd(W.size + root, 1);
+            atomicAdd(W.ends + root, (uint32_t)W.z[i]);
+            atomicMin(W.mintag + root, tg);
+        }
+        cc_st(W.parent + i, root);
+    }
+    ls = wave_sum(ls);
+    le = wave_sum(le);
+    for (int o = VBC_WAVE / 2; o > 0; o >>= 1) {
+        const int32_t v = __shfl_down(lm, o, VBC_WAVE);
+        lm = v < lm ? v : lm;
+    }
+    if ((threadIdx.x % VBC_WAVE) == 0 && ls) {
+        atomicAdd(&bsize, ls);
+        atomicAdd(&bends, le);
+        atomicMin(&bmin, lm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bsize) {
+        atomicAdd(W.size + br, (int32_t)bsize);
+        atomicAdd(W.ends + br, bends);
+        atomicMin(W.mintag + br, bmin);
+    }
+}
+
+// Per particle: its cluster's smallest tag.  Per root: the cluster's statistics and its
+// histogram bins (all clusters, acyclic clusters).
+__global__ void k_cc_label(Buffers B, Launch P, ClusterWork W, int32_t *__restrict__ label,
+                           int64_t *__restrict__ stats, int64_t *__restrict__ hist, int hist_len)
+{
+    __shared__ StageHdr S;
+    __shared__ unsigned long long tot[4];
+    __shared__ unsigned long long big;
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        tot[0] = tot[1] = tot[2] = tot[3] = 0ull;
+        big = 0ull;
+    }
+    __syncthreads();
+    if (S.overflow) return;
+    unsigned long long nc = 0, cp = 0, bonds = 0, ncyc = 0, lg = 0;
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        const int32_t root = W.parent[i];
+        if (label) label[R.o_off + B.tag[i]] = W.mintag[root];
+        if (root != (int32_t)i) continue;
+        const unsigned long long sz = (unsigned long long)W.size[i];
+        const unsigned long long e = (unsigned long long)(W.ends[i] / 2u);
+        const bool cyc = e >= sz;
+        nc += 1ull;
+        bonds += e;
+        if (cyc) {
+            cp += sz;
+            ncyc += 1ull;
+        }
+        lg = sz > lg ? sz : lg;
+        if (hist) {
+            const int bin = sz < (unsigned long long)hist_len ? (int)sz : 0;
+            int64_t *h = hist + (size_t)r * 2 * hist_len;
+            atomicAdd((unsigned long long *)(h + bin), 1ull);
+            if (!cyc) atomicAdd((unsigned long long *)(h + hist_len + bin), 1ull);
+        }
+    }
+    nc = wave_sum(nc);
+    cp = wave_sum(cp);
+    bonds = wave_sum(bonds);
+    ncyc = wave_sum(ncyc);
+    for (int o = VBC_WAVE / 2; o > 0; o >>= 1) {
+        const unsigned long long v = __shfl_down(lg, o, VBC_WAVE);
+        lg = v > lg ? v : lg;
+    }
+    if ((threadIdx.x % VBC_WAVE) == 0) {
+        atomicAdd(&tot[0], nc);
+        atomicAdd(&tot[1], cp);
+        atomicAdd(&tot[2], bonds);
+        atomicAdd(&tot[3], ncyc);
+        atomicMax(&big, lg);
+    }
+    __syncthreads();
+    if (stats && threadIdx.x == 0 && tot[0]) {
+        // only workgroups that hold a root have anything to add
+        unsigned long long *st = (unsigned long long *)(stats + 5 * (size_t)r);
+        atomicAdd(st + 0, tot[0]);
+        atomicMax(st + 1, big);
+        if (tot[1]) atomicAdd(st + 2, tot[1]);
+        if (tot[2]) atomicAdd(st + 3, tot[2]);
+        if (tot[3]) atomicAdd(st + 4, tot[3]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1635,6 +2034,12 @@ size_t lds_bytes_count(const Launch &P)
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : 16);
 }
 size_t lds_bytes_embed(const Launch &P) { return (size_t)P.bcap_max * sizeof(int); }
+// bond tests (observables, clusters): FP32 staging, then the slots or the brick's forest
+size_t lds_bytes_bonds(const Launch &P)
+{
+    return (size_t)(P.stage_cap + 1) * 16 + (size_t)std::max(P.stage_cap, P.bcap_max) * sizeof(int32_t) + 16 +
+           CC_SET * sizeof(unsigned long long);
+}
 size_t lds_bytes_force(const Launch &P)
 {
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 48 : 24);
@@ -1796,7 +2201,20 @@ hipError_t launch_observe(const Buffers &B, const Launch &P, int cur, int32_t *z
                           int32_t *pen_out, int64_t *sums, hipStream_t s)
 {
     if (sums) k_zero_i64<<<blocks_for(3 * P.nrep, 256), 256, 0, s>>>(sums, 3 * P.nrep);
-    k_observe<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, cur, z_out, pen_out, sums);
+    k_observe<<<brick_grid(P.nb_launch), P.block, lds_bytes_bonds(P), s>>>(B, P, cur, z_out, pen_out, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_clusters(const Buffers &B, const Launch &P, int cur, const ClusterWork &W,
+                           int32_t *label, int64_t *stats, int64_t *hist, int hist_len, hipStream_t s)
+{
+    if (stats) k_zero_i64<<<blocks_for(5 * P.nrep, 256), 256, 0, s>>>(stats, 5 * P.nrep);
+    if (hist) k_zero_i64<<<blocks_for(2 * (int64_t)P.nrep * hist_len, 256), 256, 0, s>>>(hist, 2 * P.nrep * hist_len);
+    k_cc_init<<<blocks_for(P.nslots, 256), 256, 0, s>>>(W, P.nslots);
+    k_cc_local<<<brick_grid(P.nb_launch), P.block, lds_bytes_bonds(P), s>>>(B, P, cur, W);
+    k_cc_hook<<<brick_grid(P.nb_launch), P.block, lds_bytes_bonds(P), s>>>(B, P, cur, W);
+    k_cc_count<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, W);
+    k_cc_label<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, W, label, stats, hist, hist_len);
     return hipGetLastError();
 }
 

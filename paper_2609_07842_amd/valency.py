@@ -1,6 +1,9 @@
 """Valency control measured on the GPU: the mean number of neighbours within the attraction
 range <z> and the fraction P_err of particles with more than f of them, against valency and
-binding strength (Section 3, Fig. 2).
+binding strength (Section 3, Fig. 2), with the connectivity of the bond graph: the giant
+component P_inf, the fraction x_cyc of particles in loop-carrying clusters, and the
+cluster-size distributions of all and of acyclic clusters next to the Flory-Stockmayer
+density of tree clusters, eq. (fs), at the measured saturation p = <z>/f (Figs. 3-5).
 
 All conditions run side by side as replicas of one handle.  Binding strength beta E_a is
 varied by scaling every energy of a replica by beta at kT = 1 (the Boltzmann weight
@@ -14,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import sys
 
 import numpy as np
@@ -22,8 +26,24 @@ from . import vbc as _vbc
 from . import workloads as W
 
 
+def fs_density(s, f, p, rho):
+    """Flory-Stockmayer number density of tree clusters of size s, eq. (fs):
+    rho w_s (1 - p)^f [p (1 - p)^(f - 2)]^(s - 1) with w_s = f (fs - s)! / ((fs - 2s + 2)! s!),
+    evaluated through log-factorials."""
+    if p <= 0.0:
+        return rho if s == 1 else 0.0
+    if p >= 1.0:
+        return 0.0
+    if (f - 2) * s + 2 < 0:
+        return 0.0  # 1 / (negative integer)! = 0: a tree of s needs s - 1 <= f s / 2 bonds
+    log_w = math.log(f) + math.lgamma((f - 1) * s + 1) - math.lgamma((f - 2) * s + 3) - math.lgamma(s + 1)
+    log_t = f * math.log1p(-p) + (s - 1) * (math.log(p) + (f - 2) * math.log1p(-p))
+    return rho * math.exp(log_w + log_t)
+
+
 def saturation_sweep(fs=(1, 2, 3, 4, 5, 6), beta_Ea=(1.0, 2.0, 4.0, 6.0, 8.0), N=10_000, rho=0.05,
-                     E_a=2.0, steps=40_000, sample_every=2_000, precision="fp32", seed=31, log=None):
+                     E_a=2.0, steps=40_000, sample_every=2_000, precision="fp32", seed=31, log=None,
+                     hist_len=64):
     say = log or (lambda m: None)
     conds = [(f, b) for f in fs for b in beta_Ea]
     L = W.box_length(N, rho)
@@ -37,6 +57,9 @@ def saturation_sweep(fs=(1, 2, 3, 4, 5, 6), beta_Ea=(1.0, 2.0, 4.0, 6.0, 8.0), N
     s = _vbc.System(reps, precision=precision, rho_max=1.0)
     s.set_state(np.concatenate(xs), np.concatenate(vs))
     z_hist = {c: [] for c in conds}
+    c_hist = {c: [] for c in conds}
+    sizes = np.zeros((len(conds), 2, hist_len), dtype=np.int64)
+    nsamp = 0
     done = 0
     while done < steps:
         s.step(sample_every, integrator="langevin", dt=0.005, kT=1.0, gamma=0.1, seed=seed)
@@ -44,15 +67,30 @@ def saturation_sweep(fs=(1, 2, 3, 4, 5, 6), beta_Ea=(1.0, 2.0, 4.0, 6.0, 8.0), N
         s.check()
         if done > steps // 2:  # second half: sample
             _, _, sums = s.observables()
-            sums = sums.cpu().numpy()
+            _, cst, hist = s.clusters(hist_len=hist_len, labels=False)
+            sums, cst = sums.cpu().numpy(), cst.cpu().numpy()
+            sizes += hist.cpu().numpy()[:len(conds)]
+            nsamp += 1
             for r, c in enumerate(conds):
                 z_hist[c].append((sums[r, 0] / N, sums[r, 1] / N, sums[r, 2] / N))
+                c_hist[c].append((cst[r, 1] / N, cst[r, 2] / N, cst[r, 0] / N))
         say(f"[valency] {done}/{steps} steps")
     out = {}
-    for c in conds:
+    V = float(L) ** 3
+    for k, c in enumerate(conds):
         h = np.array(z_hist[c])
-        out[f"f={c[0]} betaEa={c[1]:g}"] = dict(f=c[0], beta_Ea=c[1], z=float(h[:, 0].mean()),
-                                                 P_err=float(h[:, 1].mean()), penetrations=float(h[:, 2].mean()))
+        g = np.array(c_hist[c])
+        z = float(h[:, 0].mean())
+        p_sat = z / c[0]
+        # number densities of clusters of size s (index 0: sizes >= hist_len), sample mean
+        dens_all = sizes[k, 0] / (nsamp * V)
+        dens_acyc = sizes[k, 1] / (nsamp * V)
+        fs_pred = [fs_density(m, c[0], p_sat, rho) if m > 0 else None for m in range(hist_len)]
+        out[f"f={c[0]} betaEa={c[1]:g}"] = dict(
+            f=c[0], beta_Ea=c[1], z=z, P_err=float(h[:, 1].mean()), penetrations=float(h[:, 2].mean()),
+            saturation=p_sat, P_inf=float(g[:, 0].mean()), x_cyc=float(g[:, 1].mean()),
+            clusters_per_particle=float(g[:, 2].mean()),
+            rho_s_all=dens_all.tolist(), rho_s_acyclic=dens_acyc.tolist(), rho_s_fs=fs_pred)
     return dict(workload=dict(N=N, rho=rho, E_a=E_a, steps=steps, precision=precision,
                               geometry="VBC(1.5, 2.0, 0)", integrator="Langevin gamma=0.1 dt=0.005"),
                 results=out)

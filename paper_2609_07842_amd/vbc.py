@@ -30,7 +30,7 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read",
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
            "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set",
-           "vbc_observables")
+           "vbc_observables", "vbc_cluster_scratch_size", "vbc_clusters")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -114,6 +114,8 @@ def lib():
             "vbc_stamps": [vp, i32, vp],
             "vbc_tune_set": [vp, C.POINTER(Options)],
             "vbc_observables": [vp, dp, dp, dp, vp],
+            "vbc_cluster_scratch_size": [vp, C.POINTER(C.c_size_t)],
+            "vbc_clusters": [vp, dp, C.c_size_t, dp, dp, dp, i32, vp],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double)],
         }
@@ -321,6 +323,26 @@ class _Handle:
         sums = torch.empty((self.nslot, 3), dtype=torch.int64, device=self.device)
         self._ok(lib().vbc_observables(self.h, _ptr(z), _ptr(p), _ptr(sums), self._stream()))
         return z, p, sums
+
+    def clusters(self, hist_len=0, labels=True):
+        """Clusters of the bond graph (r_ij < r_a): per particle the smallest tag of its
+        cluster (int32, caller order, or None), per replica {clusters, largest, particles in
+        cyclic clusters, bonds, cyclic clusters} (int64, (slots, 5)), and for hist_len > 0 the
+        size histograms (int64, (slots, 2, hist_len): all clusters, acyclic clusters; bin 0
+        holds the sizes >= hist_len)."""
+        torch = self.torch
+        nb = C.c_size_t()
+        self._ok(lib().vbc_cluster_scratch_size(self.h, C.byref(nb)))
+        # 256-byte aligned scratch carved from one byte tensor
+        raw = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        scratch = raw[off:off + nb.value]
+        lab = torch.empty(self.stride, dtype=torch.int32, device=self.device) if labels else None
+        stats = torch.empty((self.nslot, 5), dtype=torch.int64, device=self.device)
+        hist = torch.empty((self.nslot, 2, hist_len), dtype=torch.int64, device=self.device) if hist_len else None
+        self._ok(lib().vbc_clusters(self.h, _ptr(scratch), nb.value, _ptr(lab), _ptr(stats), _ptr(hist),
+                                    int(hist_len), self._stream()))
+        return lab, stats, hist
 
     def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
         it = Integrator()

@@ -1,5 +1,6 @@
 """GPU check of valency control on a short sweep: stronger binding raises <z> towards the
-valency and lowers the fraction of over-coordinated particles (Section 3, Fig. 2)."""
+valency and lowers the fraction of over-coordinated particles (Section 3, Fig. 2), and more
+of the particles end up in loop-carrying clusters (Section 3, cyclisation)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -13,7 +14,20 @@ def test_binding_raises_coordination_towards_valency():
                                    sample_every=1000)["results"]
     for f in (1, 3):
         weak, strong = res[f"f={f} betaEa=1"], res[f"f={f} betaEa=8"]
-        print(f"[valency] f={f}: weak {weak}  strong {strong}", flush=True)
+        keys = ("z", "P_err", "saturation", "P_inf", "x_cyc")
+        print(f"[valency] f={f}: weak {[round(weak[k], 4) for k in keys]}  "
+              f"strong {[round(strong[k], 4) for k in keys]}", flush=True)
         assert strong["z"] > weak["z"]
         assert strong["z"] <= f + 0.25
     assert res["f=1 betaEa=8"]["P_err"] < 0.05
+    weak, strong = res["f=3 betaEa=1"], res["f=3 betaEa=8"]
+    assert strong["x_cyc"] > weak["x_cyc"]
+    # a valency-1 fluid holds monomers and dimers, loops only from rare transient triangles
+    assert res["f=1 betaEa=8"]["x_cyc"] < 0.03
+    import numpy as np
+    from paper_2609_07842_amd import workloads as W
+    V = W.box_length(4000, 0.05) ** 3
+    for r in res.values():
+        # the size histograms hold every cluster: their sum is the mean number of clusters
+        assert np.sum(r["rho_s_all"]) * V == pytest.approx(r["clusters_per_particle"] * 4000, rel=1e-9)
+        assert 0.0 <= r["P_inf"] <= 1.0 and 0.0 <= r["x_cyc"] <= 1.0

@@ -663,5 +663,27 @@ def test_flory_stockmayer_closed_forms():
         rs = np.array([oracle.flory_stockmayer(k, f, p, rho) for k in s_])
         assert (s_ * rs).sum() == pytest.approx(rho, rel=1e-9)
         assert rs.sum() == pytest.approx(rho * (1 - f * p / 2), rel=1e-9)
+    # f = 1: monomers rho (1 - p) and dimers rho p / 2 only
+    for p in (0.2, 0.7):
+        assert oracle.flory_stockmayer(1, 1, p, rho) == pytest.approx(rho * (1 - p), rel=1e-13)
+        assert oracle.flory_stockmayer(2, 1, p, rho) == pytest.approx(rho * p / 2, rel=1e-13)
+        assert oracle.flory_stockmayer(3, 1, p, rho) == 0.0 and oracle.flory_stockmayer(9, 1, p, rho) == 0.0
     assert oracle.flory_stockmayer(1, 4, 0.0, rho) == pytest.approx(rho, rel=1e-13)
     assert oracle.flory_stockmayer(2, 4, 0.0, rho) == 0.0
+
+
+@pytest.mark.parametrize("rho,multitype", [(0.05, False), (0.3, False), (0.4, True)])
+def test_bond_clusters_large_matches_brute_force(rho, multitype):
+    N = 900
+    L = W.box_length(N, rho)
+    x = np.mod(W.uniform_positions(N, L, 3), L)
+    if multitype:
+        types = np.random.default_rng(2).integers(0, 2, size=N).astype(np.int32)
+        pa, pb = W.vbc_params(f=2.0), dict(W.vbc_params(f=3.0), r_r=0.8, r_a=1.3, r_l=1.3, r_h=1.7)
+        pab = dict(W.vbc_params(f=1.0), r_r=0.9, r_a=1.4, r_l=1.4, r_h=1.8)
+        params = [pa, pab, pab, pb]
+    else:
+        types, params = None, W.vbc_params(f=3.0)
+    la, za = oracle.bond_clusters(x, L, params, types)
+    lb, zb = oracle.bond_clusters_large(x, L, params, types)
+    assert np.array_equal(la, lb) and np.array_equal(za, zb)
