@@ -107,10 +107,10 @@ def cpu_baseline(wl, target_s=15.0):
 def measure_clusters(s, wl, torch, kbar, reps=5):
     """Cluster analysis of the bond graph on the state the timed steps left: one warm call,
     then `reps` calls between HIP events on the launch stream.  Algorithmic bytes per
-    particle: the list (2 B per entry + 2 B count), own FP64 position and type, five int32
-    scratch arrays written by the init pass, bonds written and read, the union-find parent
-    read and written twice, the per-root atomics (size, bond ends, smallest tag), and the
-    label pass (parent, smallest tag, tag, label)."""
+    particle: two list sweeps (2 B per entry + 2 B count, own FP64 position, each), the
+    type, five int32 scratch arrays written by the init pass, bonds written and read, the
+    union-find parent written, read twice and written again, the per-root atomics (size,
+    bond ends, smallest tag), and the label pass (parent, smallest tag, tag, label)."""
     s.clusters(hist_len=4096)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -120,7 +120,7 @@ def measure_clusters(s, wl, torch, kbar, reps=5):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     st = stats.cpu().numpy()[0]
-    per_particle = 2 * kbar + 2 + 24 + 4 + 5 * 4 + 2 * 4 + 4 * 4 + 3 * 4 + 4 * 4
+    per_particle = 2 * (2 * kbar + 2 + 24) + 4 + 5 * 4 + 2 * 4 + 4 * 4 + 3 * 4 + 4 * 4
     nbytes = per_particle * wl.N
     return {"ms": ms, "clusters": int(st[0]), "P_inf": float(st[1]) / wl.N, "x_cyc": float(st[2]) / wl.N,
             "bonds_per_particle": float(st[3]) / wl.N, "bytes_model": nbytes,
