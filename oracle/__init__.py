@@ -301,6 +301,49 @@ def bond_clusters_large(x, L, params, types=None):
     return first[comp], z
 
 
+def bond_pairs(x, L, r_a):
+    """Bonds of one snapshot (Section 3 criterion, r_ij < r_a, single type) as a set of
+    index pairs (i, j), i < j, from the plain O(N^2) neighbour set."""
+    ij = neighbor_pairs(x, L, r_a)
+    return set(map(tuple, np.asarray(ij, dtype=np.int64).reshape(-1, 2).tolist()))
+
+
+class BondTracker:
+    """Bond lifetimes over a trajectory (Section 4): each bond is followed from the sample
+    at which it is first seen to the first sample without it.  Lifetimes of completed bonds
+    go to hist (bin = lifetime // bin_steps, the last bin holds the longer ones); bonds present
+    at the reset have no birth and are counted as censored when they break.
+    stats = [formed, broken with a lifetime, broken without one, 0 (no capacity limit),
+    bonds summed over the samples]."""
+
+    def __init__(self, hist_len, bin_steps):
+        self.hist = np.zeros(hist_len, dtype=np.int64)
+        self.bin_steps = int(bin_steps)
+        self.stats = np.zeros(5, dtype=np.int64)
+        self.birth = {}
+
+    def reset(self, pairs):
+        self.hist[:] = 0
+        self.stats[:] = 0
+        self.birth = {p: None for p in pairs}
+        self.stats[4] += len(pairs)
+
+    def sample(self, pairs, step):
+        for p in list(self.birth):
+            if p not in pairs:
+                b = self.birth.pop(p)
+                if b is None:
+                    self.stats[2] += 1
+                else:
+                    self.stats[1] += 1
+                    self.hist[min((step - b) // self.bin_steps, len(self.hist) - 1)] += 1
+        for p in pairs:
+            if p not in self.birth:
+                self.birth[p] = step
+                self.stats[0] += 1
+        self.stats[4] += len(pairs)
+
+
 def cluster_stats(label, z, hist_len=0):
     """Per-cluster sizes s and bond counts e (half the sum of z over the cluster); a cluster is
     cyclic when it carries a loop, e >= s (a tree has e = s - 1).

@@ -687,3 +687,38 @@ def test_bond_clusters_large_matches_brute_force(rho, multitype):
     la, za = oracle.bond_clusters(x, L, params, types)
     lb, zb = oracle.bond_clusters_large(x, L, params, types)
     assert np.array_equal(la, lb) and np.array_equal(za, zb)
+
+
+# ---------------------------------------------------------------------------
+# bond lifetimes (Section 4)
+# ---------------------------------------------------------------------------
+
+def test_bond_tracker_worked_sequence():
+    """Hand-worked sequence, samples every 10 steps: A exists at the reset and breaks at 20
+    (censored); B lives from 10 to 30 (lifetime 20, bin 2); C from 20 to 30 (lifetime 10,
+    bin 1); D from 10 to beyond the end (open, not counted); E from 10 to 80 (lifetime 70,
+    beyond the last of four bins)."""
+    A, B_, C_, D, E = (0, 1), (0, 2), (1, 3), (2, 4), (3, 4)
+    seq = {0: {A}, 10: {A, B_, D, E}, 20: {B_, C_, D, E}, 30: {D, E}, 40: {D, E}, 50: {D, E},
+           60: {D, E}, 70: {D, E}, 80: {D}}
+    t = oracle.BondTracker(hist_len=4, bin_steps=10)
+    t.reset(seq[0])
+    for step in range(10, 90, 10):
+        t.sample(seq[step], step)
+    assert t.hist.tolist() == [0, 1, 1, 1]
+    assert t.stats.tolist() == [4, 3, 1, 0, sum(len(v) for v in seq.values())]
+
+
+def test_bond_pairs_are_the_z_criterion():
+    """Every particle's number of bond pairs is its z_i, and pairs are i < j."""
+    N = 600
+    L = W.box_length(N, 0.2)
+    x = W.uniform_positions(N, L, 8)
+    pairs = oracle.bond_pairs(x, L, 1.5)
+    z = np.zeros(N, dtype=np.int64)
+    for i, j in pairs:
+        assert i < j
+        z[i] += 1
+        z[j] += 1
+    zr, _ = oracle.observables(x, L, W.vbc_params())
+    assert np.array_equal(z, zr)
