@@ -228,6 +228,28 @@ vbc_status vbc_cluster_scratch_size(vbc_handle h, size_t *bytes);
 vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int32_t *d_label,
                         int64_t *d_stats, int64_t *d_hist, int32_t hist_len, hipStream_t s);
 
+/* Bond lifetimes (Section 4, "Bond lifetimes"): one sample of a tracker that follows every
+ * bond (r_ij < r_a of the pair, the criterion of vbc_observables) from the first sample at
+ * which it is seen to the first sample without it, at the replicas' current step counters.
+ *   d_state        device memory of vbc_bond_track_size bytes, 256-byte aligned, owned by the
+ *                  caller and kept between calls: per caller index the count of stored
+ *                  partners, their tags and the steps their bonds were first seen
+ *   max_partners   bonds stored per particle, 1..64; bonds that do not fit are counted
+ *   reset          nonzero: start tracking from the current bonds (their births unknown)
+ *                  and zero d_hist and d_stats; call it after set_state or an admission
+ *   d_hist         device int64 [slots][hist_len], or NULL: completed bonds (first seen at a
+ *                  sample, gone at a later one) by lifetime in steps / bin_steps; the last bin
+ *                  holds the longer ones
+ *   d_stats        device int64 [slots][5], or NULL: bonds formed, bonds broken with a
+ *                  lifetime, bonds broken that existed at the reset, bonds that did not fit,
+ *                  bonds summed over the samples
+ * Each bond is counted once, at its end with the smaller tag.  d_hist and d_stats add up
+ * over the calls after a reset.  Rebuilds the list first if it is stale.  Asynchronous on s;
+ * returns VBC_ERR_ARG for a missing, small or misaligned state or bad sizes. */
+vbc_status vbc_bond_track_size(vbc_handle h, int32_t max_partners, size_t *bytes);
+vbc_status vbc_bond_track(vbc_handle h, void *d_state, size_t state_bytes, int32_t max_partners, int32_t reset,
+                          int64_t *d_hist, int32_t hist_len, int64_t bin_steps, int64_t *d_stats, hipStream_t s);
+
 /* Layout actually chosen (after automatic choices): k_max, brick edge, block, stage_cap. */
 vbc_status vbc_get_options(vbc_handle h, vbc_options *out);
 

@@ -1308,6 +1308,45 @@ vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int
     return VBC_OK;
 }
 
+static size_t track_part(size_t b) { return (b + 255) & ~(size_t)255; }
+
+vbc_status vbc_bond_track_size(vbc_handle h, int32_t max_partners, size_t *bytes)
+{
+    if (!h || !bytes) return fail(VBC_ERR_ARG, "NULL argument");
+    if (max_partners < 1 || max_partners > 64) return hfail(h, VBC_ERR_ARG, "max_partners must be 1..64");
+    const size_t n = (size_t)h->P.ntot;
+    *bytes = track_part(n * 4) + track_part(n * max_partners * 4) + track_part(n * max_partners * 8);
+    return VBC_OK;
+}
+
+vbc_status vbc_bond_track(vbc_handle h, void *d_state, size_t state_bytes, int32_t max_partners, int32_t reset,
+                          int64_t *d_hist, int32_t hist_len, int64_t bin_steps, int64_t *d_stats, hipStream_t s)
+{
+    if (!h || !d_state) return fail(VBC_ERR_ARG, "NULL argument");
+    size_t need = 0;
+    vbc_status st = vbc_bond_track_size(h, max_partners, &need);
+    if (st != VBC_OK) return st;
+    if (state_bytes < need) return hfail(h, VBC_ERR_ARG, "tracker state too small: vbc_bond_track_size gives the size");
+    if (((uintptr_t)d_state & 255) != 0) return hfail(h, VBC_ERR_ARG, "tracker state must be 256-byte aligned");
+    if (d_hist && (hist_len < 1 || (int64_t)h->P.nrep * hist_len > INT32_MAX))
+        return hfail(h, VBC_ERR_ARG, "hist_len must be >= 1, and slots x hist_len below 2^31, when d_hist is given");
+    if (d_hist && bin_steps < 1) return hfail(h, VBC_ERR_ARG, "bin_steps must be >= 1");
+    VBC_NEED_STATE(h);
+    VBC_LAYOUT(h, s);
+    VBC_TRY(h, timed(h, VBC_K_BUILD, s, [&] { return launch_rebuild(h->B, h->P, h->cur, s); }), "rebuild");
+    const size_t n = (size_t)h->P.ntot;
+    char *base = (char *)d_state;
+    BondTrack T;
+    T.count = (int32_t *)base;
+    T.tags = (int32_t *)(base + track_part(n * 4));
+    T.births = (int64_t *)(base + track_part(n * 4) + track_part(n * max_partners * 4));
+    T.M = max_partners;
+    VBC_TRY(h, launch_bond_track(h->B, h->P, h->cur, T, reset ? 1 : 0, d_hist, d_hist ? hist_len : 0,
+                                 bin_steps, d_stats, s),
+            "bond tracker");
+    return VBC_OK;
+}
+
 vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out)
 {
     if (!h || !out) return fail(VBC_ERR_ARG, "NULL argument");

@@ -186,6 +186,16 @@ struct ClusterWork {
     int32_t *mintag;  // smallest caller tag per cluster
     int32_t *z;       // bonds of every particle
 };
+// State of the bond tracker, by caller index: partner count, then M partner tags and M
+// birth steps per particle.
+struct BondTrack {
+    int32_t *count;   // [ntot]
+    int32_t *tags;    // [ntot][M]
+    int64_t *births;  // [ntot][M]
+    int M;
+};
+hipError_t launch_bond_track(const Buffers &B, const Launch &P, int cur, const BondTrack &T, int reset,
+                             int64_t *hist, int hist_len, int64_t bin_steps, int64_t *stats, hipStream_t s);
 hipError_t launch_clusters(const Buffers &B, const Launch &P, int cur, const ClusterWork &W,
                            int32_t *label, int64_t *stats, int64_t *hist, int hist_len, hipStream_t s);
 size_t lds_bytes_sort(const Launch &P);

@@ -2010,6 +2010,139 @@ __global__ void k_cc_label(Buffers B, Launch P, ClusterWork W, int32_t *__restri
 }
 
 // ---------------------------------------------------------------------------
+// bond lifetimes (Section 4): partners of every particle carried from sample to sample
+// ---------------------------------------------------------------------------
+
+// One sample of the bond tracker.  For every own particle the state (by caller index) holds
+// up to M partner tags with the step each bond was first seen (-1: present when tracking
+// began).  A stored partner that is no longer bonded is a broken bond: its lifetime goes to
+// the replica's histogram (bin = lifetime / bin_steps, the last bin holds the longer ones),
+// or to the censored count without a birth.  A bonded particle not stored is a new bond,
+// born now.  Each event is counted at the end with the smaller tag, once per bond.
+// stats per replica: {formed, broken with a lifetime, broken without one, partners that did
+// not fit, bonds now}.
+__global__ void k_bond_track(Buffers B, Launch P, int cur, BondTrack T, int reset,
+                             int64_t *__restrict__ hist, int hist_len, int64_t bin_steps,
+                             int64_t *__restrict__ stats)
+{
+    extern __shared__ __align__(16) float4 spos[];  // [stage_cap + 1], then stag[stage_cap]
+    __shared__ StageHdr S;
+    __shared__ unsigned long long tot[5];
+    int b, r;
+    if (!resolve_brick(P, B, b, r)) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    if (threadIdx.x == 0) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        for (int k = 0; k < 5; ++k) tot[k] = 0ull;
+    }
+    __syncthreads();
+    if (S.overflow) return;
+    const int64_t S_ = P.nslots;
+    const double *X = B.x[cur];
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    int32_t *stag = (int32_t *)(spos + P.stage_cap + 1);
+    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
+        spos[t] = local_pos<float>(R, S, X, S_, src, w, B.type[src]);
+        stag[t] = B.tag[src];
+    });
+    if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<float4>();
+    __syncthreads();
+    const bool one = R.ntypes == 1;
+    const Band ba0 = make_band(R.pair[0].ra2);
+    const int M = T.M;
+    const int64_t now = (int64_t)B.step[r];
+    unsigned long long formed = 0, broken = 0, cens = 0, over = 0, bonds = 0;
+    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
+        const int64_t i = S.base + t;
+        const float4 pi = spos[t];
+        const int ti = (int)pi.w;
+        const int32_t tg = stag[t];
+        const int64_t c = R.o_off + tg;
+        int32_t *ptag = T.tags + c * M;
+        int64_t *pbirth = T.births + c * M;
+        auto bonded = [&](int u) {
+            const float4 pj = spos[u];
+            const float r2f = staged_r2(pi, pj);
+            const Band ba = one ? ba0 : make_band(R.pair[ti * MAXT + (int)pj.w].ra2);
+            return r2f < ba.hi && within(r2f, ba, R, X, S_, i, sm[u]);
+        };
+        int n = 0;
+        if (!reset) {
+            // 1. which stored partners are still bonded
+            const int n_old = min(max(T.count[c], 0), M);
+            uint64_t keep = 0ull;
+            for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+                if (R.excl_span > 0) u &= 0x7fff;
+                if (u == P.stage_cap || !bonded(u)) return;
+                const int32_t tj = stag[u];
+                for (int k = 0; k < n_old; ++k)
+                    if (ptag[k] == tj) {
+                        keep |= 1ull << k;
+                        break;
+                    }
+            });
+            // 2. broken bonds leave, the others close up in order
+            for (int k = 0; k < n_old; ++k) {
+                const int32_t tk = ptag[k];
+                const int64_t bk = pbirth[k];
+                if ((keep >> k) & 1ull) {
+                    ptag[n] = tk;
+                    pbirth[n] = bk;
+                    ++n;
+                } else if (tg < tk) {
+                    if (bk >= 0) {
+                        ++broken;
+                        if (hist) {
+                            const int64_t bin = (now - bk) / bin_steps;
+                            atomicAdd((unsigned long long *)(hist + (size_t)r * hist_len +
+                                                             (bin < hist_len - 1 ? bin : hist_len - 1)),
+                                      1ull);
+                        }
+                    } else {
+                        ++cens;
+                    }
+                }
+            }
+        }
+        // 3. bonds not stored are new (at a reset: present from the start, birth unknown)
+        const int n_keep = n;
+        for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
+            if (R.excl_span > 0) u &= 0x7fff;
+            if (u == P.stage_cap || !bonded(u)) return;
+            const int32_t tj = stag[u];
+            if (tg < tj) ++bonds;
+            for (int k = 0; k < n_keep; ++k)
+                if (ptag[k] == tj) return;
+            if (n < M) {
+                ptag[n] = tj;
+                pbirth[n] = reset ? (int64_t)-1 : now;
+                ++n;
+                if (!reset && tg < tj) ++formed;
+            } else {
+                ++over;
+            }
+        });
+        T.count[c] = n;
+    }
+    formed = wave_sum(formed);
+    broken = wave_sum(broken);
+    cens = wave_sum(cens);
+    over = wave_sum(over);
+    bonds = wave_sum(bonds);
+    if ((threadIdx.x % VBC_WAVE) == 0) {
+        atomicAdd(&tot[0], formed);
+        atomicAdd(&tot[1], broken);
+        atomicAdd(&tot[2], cens);
+        atomicAdd(&tot[3], over);
+        atomicAdd(&tot[4], bonds);
+    }
+    __syncthreads();
+    if (stats && threadIdx.x < 5 && tot[threadIdx.x])
+        atomicAdd((unsigned long long *)(stats + 5 * (size_t)r + threadIdx.x), tot[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -2215,6 +2348,16 @@ hipError_t launch_clusters(const Buffers &B, const Launch &P, int cur, const Clu
     k_cc_hook<<<brick_grid(P.nb_launch), P.block, lds_bytes_bonds(P), s>>>(B, P, cur, W);
     k_cc_count<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, W);
     k_cc_label<<<brick_grid(P.nb_launch), P.block, 0, s>>>(B, P, W, label, stats, hist, hist_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_bond_track(const Buffers &B, const Launch &P, int cur, const BondTrack &T, int reset,
+                             int64_t *hist, int hist_len, int64_t bin_steps, int64_t *stats, hipStream_t s)
+{
+    if (reset && stats) k_zero_i64<<<blocks_for(5 * P.nrep, 256), 256, 0, s>>>(stats, 5 * P.nrep);
+    if (reset && hist) k_zero_i64<<<blocks_for((int64_t)P.nrep * hist_len, 256), 256, 0, s>>>(hist, P.nrep * hist_len);
+    k_bond_track<<<brick_grid(P.nb_launch), P.block, lds_bytes_bonds(P), s>>>(B, P, cur, T, reset, hist, hist_len,
+                                                                              bin_steps, stats);
     return hipGetLastError();
 }
 

@@ -30,7 +30,8 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_get_nlist", "vbc_get_options", "vbc_get_stats", "vbc_profile", "vbc_profile_read",
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
            "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set",
-           "vbc_observables", "vbc_cluster_scratch_size", "vbc_clusters")
+           "vbc_observables", "vbc_cluster_scratch_size", "vbc_clusters", "vbc_bond_track_size",
+           "vbc_bond_track")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -116,6 +117,8 @@ def lib():
             "vbc_observables": [vp, dp, dp, dp, vp],
             "vbc_cluster_scratch_size": [vp, C.POINTER(C.c_size_t)],
             "vbc_clusters": [vp, dp, C.c_size_t, dp, dp, dp, i32, vp],
+            "vbc_bond_track_size": [vp, i32, C.POINTER(C.c_size_t)],
+            "vbc_bond_track": [vp, dp, C.c_size_t, i32, i32, dp, i32, i64, dp, vp],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double)],
         }
@@ -344,6 +347,12 @@ class _Handle:
                                     int(hist_len), self._stream()))
         return lab, stats, hist
 
+    def bond_tracker(self, max_partners=16, hist_len=4096, bin_steps=1):
+        """A bond-lifetime tracker over this handle's replicas (reset at once from the
+        current bonds); call .sample() after steps, read .hist (slots, hist_len) and .stats
+        (slots, 5) as int64 tensors."""
+        return BondTracker(self, max_partners, hist_len, bin_steps)
+
     def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
         it = Integrator()
         it.kind = NVE if integrator in ("nve", NVE) else LANGEVIN
@@ -393,6 +402,38 @@ class _Handle:
         self._ok(lib().vbc_get_nlist(self.h, rep, _ptr(pairs), int(cap), _ptr(cnt), self._stream()))
         c = int(cnt.item())
         return pairs[: min(c, cap)].cpu().numpy(), c
+
+
+class BondTracker:
+    """State of vbc_bond_track for one handle (see include/vbc.h)."""
+
+    def __init__(self, handle, max_partners, hist_len, bin_steps):
+        torch = handle.torch
+        self.h = handle
+        self.M, self.hist_len, self.bin_steps = int(max_partners), int(hist_len), int(bin_steps)
+        nb = C.c_size_t()
+        handle._ok(lib().vbc_bond_track_size(handle.h, self.M, C.byref(nb)))
+        self._raw = torch.empty(nb.value + 256, dtype=torch.uint8, device=handle.device)
+        off = (-self._raw.data_ptr()) % 256
+        self.state = self._raw[off:off + nb.value]
+        self.hist = torch.empty((handle.nslot, self.hist_len), dtype=torch.int64, device=handle.device)
+        self.stats = torch.empty((handle.nslot, 5), dtype=torch.int64, device=handle.device)
+        self.sample(reset=True)
+
+    def sample(self, reset=False):
+        h = self.h
+        h._ok(lib().vbc_bond_track(h.h, _ptr(self.state), self.state.numel(), self.M, 1 if reset else 0,
+                                   _ptr(self.hist), self.hist_len, self.bin_steps, _ptr(self.stats), h._stream()))
+
+    def median_lifetime(self, rep=0):
+        """Median completed lifetime in steps, as the lower edge of its bin (exact when the
+        samples are bin_steps apart), or None without any completed bond."""
+        h = self.hist[rep].cpu().numpy()
+        tot = int(h.sum())
+        if tot == 0:
+            return None
+        k = int((h.cumsum() >= (tot + 1) // 2).argmax())
+        return float(k * self.bin_steps)
 
 
 class System(_Handle):
@@ -455,13 +496,13 @@ class Pool(_Handle):
     others keep running (vbc_pool_create)."""
 
     def __init__(self, caps, precision="fp32", k_max=0, stage_cap=0, brick=0, block=0,
-                 device="cuda"):
+                 rho_max=0.0, device="cuda"):
         self._init_common(device)
         self.caps = dict(caps)
         c = _caps(**caps)
         self.nslot = c.max_replicas
         self.stride = c.max_particles
-        o = _options(precision, k_max, brick, block, stage_cap)
+        o = _options(precision, k_max, brick, block, stage_cap, rho_max)
         n = C.c_size_t(0)
         _check(lib().vbc_pool_workspace_size(C.byref(c), C.byref(o), C.byref(n)))
         self._alloc_ws(n.value)
