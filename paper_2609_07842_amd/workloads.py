@@ -34,6 +34,13 @@ def exchange_tuned(**kw):
     return vbc_params(**base)
 
 
+def exchange_dt(f):
+    """Time step for the exchange-tuned geometry (Section 4): 0.01 for valencies 1 and 2 (as
+    for the standard geometry), 0.005 from valency 3 on, where the steeper switching of
+    VBC(1.29, 1.50, 0.30) needs the shorter step."""
+    return 0.01 if f <= 2 else 0.005
+
+
 def stability_sets(E_a=1.0):
     """The four counter geometries compared in the stability study (Section 6.2)."""
     return {
