@@ -80,3 +80,19 @@ def test_bond_tracker_in_a_pool_and_capacity():
     pool.step(10, integrator="langevin", seed=5)
     small.sample()
     assert small.stats.cpu().numpy()[rb, 3] > 0
+
+
+def test_lifetime_sweep_exchange_geometry_repartners_faster():
+    """Section 4, Fig. 7: bond lifetimes grow with saturation for the standard geometry,
+    while VBC(1.29, 1.50, 0.30) keeps them short under strong binding."""
+    from paper_2609_07842_amd import lifetimes
+    res = lifetimes.lifetime_sweep(fs=(1,), beta_Ea=(1.0, 8.0), N=2000, equil=4000, steps=8000,
+                                   every=10)["results"]
+    for k, v in res.items():
+        print(f"[lifetimes] {k}: p {v['saturation']:.3f} tau_rate {v['tau_rate']:.1f} "
+              f"tau_median {v['tau_median']}", flush=True)
+        assert v["overflow"] == 0
+    std_w, std_s = res["standard f=1 betaEa=1"], res["standard f=1 betaEa=8"]
+    tun_s = res["exchange f=1 betaEa=8"]
+    assert std_s["saturation"] > std_w["saturation"] and std_s["tau_rate"] > 5 * std_w["tau_rate"]
+    assert tun_s["tau_rate"] < std_s["tau_rate"] / 5
