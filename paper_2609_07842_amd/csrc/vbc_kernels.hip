@@ -806,8 +806,10 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
         int loc = B.lcells[i];
         int lx = loc % S.e[0], ly = (loc / S.e[0]) % S.e[1], lz = loc / (S.e[0] * S.e[1]);
         float4 pi = spos[t];
-        int nn = 0;
-        uint32_t buf[4] = {0u, 0u, 0u, 0u};
+        int nn = 0, e = 0;
+        // the open chunk as one 128-bit shift register, newest entry in the low half of b0
+        uint32_t b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
+        uint4 *wp = B.nl + i;  // where the open chunk goes
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy)
                 for (int dx = 0; dx < 3; ++dx) {
@@ -838,7 +840,6 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
                             in = r2 < rl2;
                         }
                         if (in) {
-                            int e = nn & (CHUNK - 1);
                             uint32_t hv = (uint32_t)u;
                             if (xspan > 0) {
                                 // chain neighbours up to excl_span beads apart: bit 15
@@ -846,32 +847,29 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
                                 const int db = ta - tb;
                                 if (ta / cl == tb / cl && db <= xspan && -db <= xspan) hv |= 0x8000u;
                             }
-                            hv <<= 16 * (e & 1);
-                            if (e < 2) buf[0] |= hv;
-                            else if (e < 4) buf[1] |= hv;
-                            else if (e < 6) buf[2] |= hv;
-                            else buf[3] |= hv;
+                            b3 = __builtin_amdgcn_alignbit(b3, b2, 16);
+                            b2 = __builtin_amdgcn_alignbit(b2, b1, 16);
+                            b1 = __builtin_amdgcn_alignbit(b1, b0, 16);
+                            b0 = (b0 << 16) | hv;
                             ++nn;
-                            if ((nn & (CHUNK - 1)) == 0) {
-                                if (nn <= kmax)
-                                    B.nl[(size_t)(nn / CHUNK - 1) * S_ + i] =
-                                        make_uint4(buf[0], buf[1], buf[2], buf[3]);
-                                buf[0] = buf[1] = buf[2] = buf[3] = 0u;
+                            if (++e == CHUNK) {
+                                if (nn <= kmax) *wp = make_uint4(b0, b1, b2, b3);
+                                wp += S_;
+                                e = 0;
                             }
                         }
                     }
                 }
-        if ((nn & (CHUNK - 1)) && nn <= kmax) {
+        if (e && nn <= kmax) {
             // pad the last chunk with the dummy staged slot (far away: contributes nothing)
             const uint32_t D = (uint32_t)P.stage_cap;
-            for (int e = nn & (CHUNK - 1); e < CHUNK; ++e) {
-                uint32_t hv = D << (16 * (e & 1));
-                if (e < 2) buf[0] |= hv;
-                else if (e < 4) buf[1] |= hv;
-                else if (e < 6) buf[2] |= hv;
-                else buf[3] |= hv;
+            for (; e < CHUNK; ++e) {
+                b3 = __builtin_amdgcn_alignbit(b3, b2, 16);
+                b2 = __builtin_amdgcn_alignbit(b2, b1, 16);
+                b1 = __builtin_amdgcn_alignbit(b1, b0, 16);
+                b0 = (b0 << 16) | D;
             }
-            B.nl[(size_t)(nn / CHUNK) * S_ + i] = make_uint4(buf[0], buf[1], buf[2], buf[3]);
+            *wp = make_uint4(b0, b1, b2, b3);
         }
         if (nn > kmax) {
             ovf = true;
@@ -1037,6 +1035,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
 
     const PairR<Real> p0 = pt[0];
     const bool xr = R.excl_span > 0;  // list entries carry the exclusion bit 15
+    // read once: the global descriptor cannot be kept in registers across the stores below
+    const double wx1 = R.pair[0].x1, wx2 = R.pair[0].x2;
+    const bool watt = R.pair[0].attract;
+    const int64_t o_off = R.o_off;
     bool win = false;
     unsigned long long evals = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -1087,11 +1089,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
                 if (pd.attract && n > pd.x1 && n < pd.x2) win = true;
             }
         } else {
-            const PairDev &pd = R.pair[0];
-            sA[i] = R2{(Real)omega_d64(n, pd.x1, pd.x2), Real(0)};
-            if (pd.attract && n > pd.x1 && n < pd.x2) win = true;
+            sA[i] = R2{(Real)omega_d64(n, wx1, wx2), Real(0)};
+            if (watt && n > wx1 && n < wx2) win = true;
         }
-        if (n_out) n_out[R.o_off + B.tag[i]] = n;
+        if (n_out) n_out[o_off + B.tag[i]] = n;
     }
     if (win) any_win = 1;
     if (STATS) {
@@ -1284,6 +1285,10 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
 
     const PairR<Real> p0 = pt[0];
     const bool xr = R.excl_span > 0;  // list entries carry the exclusion bit 15
+    // read once: the global descriptor cannot be kept in registers across the stores below
+    const int chain_len = R.chain_len;
+    const double disp2 = R.disp2;
+    const int64_t o_off = R.o_off;
     const uint64_t step = B.step[r];
     const uint64_t key = st.seed + R.seed;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
@@ -1369,12 +1374,12 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         double eb = 0.0, wb[7] = {0, 0, 0, 0, 0, 0, 0};
         double xi_[3] = {X[i], X[S_ + i], X[2 * S_ + i]};
         int32_t tg = B.tag[i];
-        if (R.chain_len > 1) {
+        if (chain_len > 1) {
             // harmonic bonds to the neighbouring beads of the same chain
-            int bead = tg % R.chain_len;
+            int bead = tg % chain_len;
             for (int side = -1; side <= 1; side += 2) {
-                if ((side < 0 && bead == 0) || (side > 0 && bead == R.chain_len - 1)) continue;
-                int64_t j = B.inv[R.o_off + tg + side];
+                if ((side < 0 && bead == 0) || (side > 0 && bead == chain_len - 1)) continue;
+                int64_t j = B.inv[o_off + tg + side];
                 double d[3];
                 for (int a = 0; a < 3; ++a) {
                     double tt = xi_[a] - X[a * S_ + j];
@@ -1407,12 +1412,12 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
             acc[5] += 0.5 * (double)wxy + wb[4];
             acc[6] += 0.5 * (double)wxz + wb[5];
             acc[7] += 0.5 * (double)wyz + wb[6];
-            if (e_out) e_out[R.o_off + tg] = e_i;
+            if (e_out) e_out[o_off + tg] = e_i;
         }
         if (mode == MODE_EVAL) {
             for (int a = 0; a < 3; ++a) B.Fst[a * S_ + i] = F[a];
             if (F_out)
-                for (int a = 0; a < 3; ++a) F_out[a * ntot + R.o_off + tg] = F[a];
+                for (int a = 0; a < 3; ++a) F_out[a * ntot + o_off + tg] = F[a];
         } else {
             double vv[3] = {B.v[i], B.v[S_ + i], B.v[2 * S_ + i]};
             double xx[3] = {xi_[0], xi_[1], xi_[2]};
@@ -1428,7 +1433,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                     double dd = xx[a] - B.xref[a * S_ + i];
                     d2 += dd * dd;
                 }
-                if (d2 > R.disp2) mv = true;
+                if (d2 > disp2) mv = true;
             }
         }
     }
@@ -1542,11 +1547,6 @@ __global__ void k_zero_i64(int64_t *p, int n)
     if (k < n) p[k] = 0;
 }
 
-// Observables of valency control: for every own particle the number of list neighbours
-// within the attraction range and within the repulsive core of the pair, decided in FP64
-// on the wrapped positions exactly as the plain definition (t = x_i - x_j,
-// d = t - L rint(t / L), r^2 = (dx dx + dy dy) + dz dz, r^2 < r * r), plus per-replica sums
-// {sum z, #(z > f), sum p}.  The list holds every pair within the interaction cutoff.
 // Squared minimum-image distance from the wrapped position wi of a particle to slot j, in
 // FP64 with the operations of the plain definition (round-half-even image, no contraction):
 // the bond criterion of the observables and of the cluster analysis.
@@ -1569,12 +1569,6 @@ __device__ __forceinline__ double obs_r2(const RepDev &R, const double *__restri
         d[a] = tt - La * k;
     }
     return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-}
-
-// Squared attraction range of the pair (type of own particle i, type of slot j).
-__device__ __forceinline__ double pair_ra2(const RepDev &R, const Buffers &B, int ti, int64_t j)
-{
-    return R.ntypes == 1 ? R.pair[0].ra2 : R.pair[ti * MAXT + B.type[j]].ra2;
 }
 
 // Brick-local FP32 positions (type in w) of every particle the brick staged at the last
@@ -1619,6 +1613,11 @@ __device__ __forceinline__ float staged_r2(const float4 &a, const float4 &b)
     return dx * dx + dy * dy + dz * dz;
 }
 
+// Observables of valency control: for every own particle the number of list neighbours
+// within the attraction range and within the repulsive core of the pair, each threshold
+// decided by `within` (exactly as the plain FP64 definition on the wrapped positions), plus
+// per-replica sums {sum z, #(z > f), sum p}.  The list holds every pair within the
+// interaction cutoff.
 __global__ void k_observe(Buffers B, Launch P, int cur, int32_t *__restrict__ z_out,
                           int32_t *__restrict__ pen_out, int64_t *__restrict__ sums)
 {
