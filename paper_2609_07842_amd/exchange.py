@@ -1,23 +1,28 @@
-"""Energy along the partner-exchange path (Section 4): a centre saturated with f bonds
+"""Energy landscape of the partner exchange (Section 4): a centre saturated with f bonds
 trades one partner for a free particle, all three on one line.  The centre sits at the
 origin with f - 1 spectator partners at the well minimum m = (r_r + r_a) / 2 on +y, -y, +z,
--z (so f <= 5); partner A starts at +m on the x axis and the newcomer B at -d, beyond every
-range of the potential (d = max(r_a, r_h) + 0.5).  Along the path (lambda from 0 to 1) A moves
-out to +d and B in to -m, both linearly, so the path is symmetric (U(0) = U(1)).
+-z (so f <= 5); the leaving partner A sits at +r_A and the newcomer B at -r_B on the x axis.
+U(r_A, r_B) is evaluated on a square grid of both distances from 0.9 r_r to
+d = max(r_a, r_h) + 0.5, beyond every range of the potential.
 
-The barrier is max U(lambda) - U(0).  A trap is a local minimum of U strictly inside the
-path that lies below U(0): a bound state of the saturated centre with an extra particle.
-Every point of the path is one replica of a single handle, so a scan over geometries is a
-few force evaluations on the GPU.
+* The two bonded states are the minima of U(r_A, d) (A bonded, B away) and of U(d, r_B);
+  they are equal by symmetry.
+* The exchange barrier is the height, above that minimum, of the lowest path between them
+  on the grid: the minimax (bottleneck) path, found by adding grid points in order of
+  energy until the two states connect.
+* A trap is a grid state with both A and B inside the attraction range that lies below
+  the bonded state: an extra particle bound to an already saturated centre.
 
-    python -m paper_2609_07842_amd.exchange [--points 81]
+Every grid point is one replica of a batched handle, so a whole landscape is one force
+evaluation per 1024 points on the GPU.
+
+    python -m paper_2609_07842_amd.exchange [--points 41]
 """
 from __future__ import annotations
 
 import argparse
 import itertools
 import json
-import sys
 
 import numpy as np
 
@@ -28,77 +33,125 @@ SPECTATORS = np.array([[0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=np.f
 BOX = 24.0
 
 
-def path_positions(params, f, lam):
-    """Positions (f + 2, 3) at path parameter lam, shifted to the box centre: centre, A, B,
-    then the f - 1 spectators."""
-    if not 1 <= f <= 5:
-        raise ValueError("the path places at most four spectators: f must be 1..5")
-    m = 0.5 * (params["r_r"] + params["r_a"])
+def grid_radii(params, points):
     d = max(params["r_a"], params["r_h"]) + 0.5
+    return np.linspace(0.9 * params["r_r"], d, points)
+
+
+def positions(params, f, r_A, r_B):
+    """Positions (f + 2, 3), shifted to the box centre: centre, A, B, then the f - 1
+    spectators."""
+    if not 1 <= f <= 5:
+        raise ValueError("the spectators cover at most four directions: f must be 1..5")
+    m = 0.5 * (params["r_r"] + params["r_a"])
     x = np.zeros((f + 2, 3))
-    x[1, 0] = m + lam * (d - m)
-    x[2, 0] = -(d - lam * (d - m))
+    x[1, 0] = r_A
+    x[2, 0] = -r_B
     x[3:] = m * SPECTATORS[:f - 1]
     return x + BOX / 2
 
 
-def profiles(geoms, fs, points=81, E_a=2.0, precision="fp64"):
-    """U(lambda) for every (geometry, f): geoms is a list of (r_l, r_h, delta).  Returns an
-    array [len(geoms), len(fs), points]."""
-    lams = np.linspace(0.0, 1.0, points)
-    jobs = [(g, f, lam) for g in geoms for f in fs for lam in lams]
+def landscapes(geoms, fs, points=41, E_a=2.0, precision="fp64"):
+    """U(r_A, r_B) for every (geometry, f), geoms a list of (r_l, r_h, delta): array
+    [len(geoms), len(fs), points, points] and the radii of each geometry."""
+    radii, jobs = [], []
+    for g in geoms:
+        p = W.vbc_params(E_a=E_a, r_l=g[0], r_h=g[1], delta=g[2])
+        r = grid_radii(p, points)
+        radii.append(r)
+        for f in fs:
+            for a in r:
+                for b in r:
+                    jobs.append((g, f, a, b))
     U = np.empty(len(jobs))
     for c0 in range(0, len(jobs), 1024):
         chunk = jobs[c0:c0 + 1024]
         reps, xs = [], []
-        for (rl, rh, dl), f, lam in chunk:
+        for (rl, rh, dl), f, a, b in chunk:
             p = W.vbc_params(E_a=E_a, f=float(f), r_l=rl, r_h=rh, delta=dl)
             reps.append(_vbc.replica(f + 2, BOX, p))
-            xs.append(path_positions(p, f, lam))
+            xs.append(positions(p, f, a, b))
         s = _vbc.System(reps, precision=precision)
         s.set_state(np.concatenate(xs))
         _, _, UW = s.force()
         s.check()
         U[c0:c0 + len(chunk)] = UW.cpu().numpy()[:len(chunk), 0]
         s.close()
-    return U.reshape(len(geoms), len(fs), points)
+    return U.reshape(len(geoms), len(fs), points, points), radii
 
 
-def barrier_and_trap(u):
-    """Barrier max U - U(0) and whether a local minimum inside the path lies below U(0)."""
-    inner = u[1:-1]
-    is_min = (inner < u[:-2]) & (inner <= u[2:])
-    trap = bool(np.any(is_min & (inner < u[0] - 1e-12)))
-    return float(u.max() - u[0]), trap
+def bottleneck(U, src, dst):
+    """Lowest possible maximum of U along a path between grid points src and dst (steps to
+    the 8 neighbours): points are added in order of energy, joined by union-find, until src
+    and dst are connected."""
+    n0, n1 = U.shape
+    parent = np.arange(n0 * n1)
+
+    def find(k):
+        while parent[k] != k:
+            parent[k] = parent[parent[k]]
+            k = parent[k]
+        return k
+
+    on = np.zeros(n0 * n1, dtype=bool)
+    s, t = src[0] * n1 + src[1], dst[0] * n1 + dst[1]
+    for k in np.argsort(U, axis=None, kind="stable"):
+        on[k] = True
+        i, j = divmod(int(k), n1)
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                a, b = i + di, j + dj
+                if (di or dj) and 0 <= a < n0 and 0 <= b < n1 and on[a * n1 + b]:
+                    ra, rb = find(k), find(a * n1 + b)
+                    if ra != rb:
+                        parent[ra] = rb
+        if on[s] and on[t] and find(s) == find(t):
+            return float(U.flat[k])
+    return float("inf")
 
 
-def scan(r_l=np.round(np.arange(1.20, 1.51, 0.03), 2), r_h=np.round(np.arange(1.40, 2.01, 0.05), 2),
-         delta=(0.0, 0.1, 0.2, 0.3, 0.4), fs=(1, 2, 3, 4, 5), points=41, E_a=2.0):
-    """Barrier of every geometry r_l < r_h in the grid at every valency; the objective is the
-    worst barrier over the valencies, geometries with a trap at any valency excluded."""
+def barrier_and_trap(U, r, r_a):
+    """(barrier above the bonded state, trap present) of one landscape U[r_A, r_B]."""
+    far = len(r) - 1
+    ia = int(np.argmin(U[:, far]))          # A bonded, B away
+    ib = int(np.argmin(U[far, :]))          # B bonded, A away
+    u0 = min(U[ia, far], U[far, ib])
+    saddle = bottleneck(U, (ia, far), (far, ib))
+    both = (r < r_a)[:, None] & (r < r_a)[None, :]
+    trap = bool(np.any(U[both] < u0 - 1e-9))
+    return saddle - u0, trap
+
+
+def scan(r_l=(1.20, 1.25, 1.29, 1.35, 1.40, 1.45, 1.50), r_h=(1.40, 1.50, 1.60, 1.70, 1.80, 1.90, 2.00),
+         delta=(0.0, 0.15, 0.30, 0.45), fs=(1, 2, 3, 4, 5), points=21, E_a=2.0):
+    """Barrier of every geometry r_l < r_h of the grid at every valency; the objective is the
+    worst barrier over the valencies among geometries without a trap at any of them."""
     geoms = [g for g in itertools.product(r_l, r_h, delta) if g[0] < g[1]]
-    U = profiles(geoms, fs, points, E_a)
+    U, radii = landscapes(geoms, fs, points, E_a)
     rows = []
     for k, g in enumerate(geoms):
-        bt = [barrier_and_trap(U[k, j]) for j in range(len(fs))]
-        rows.append(dict(r_l=float(g[0]), r_h=float(g[1]), delta=float(g[2]),
-                         barriers=[b for b, _ in bt], trap=any(t for _, t in bt),
-                         worst=max(b for b, _ in bt)))
+        bt = [barrier_and_trap(U[k, j], radii[k], 1.5) for j in range(len(fs))]
+        rows.append(dict(r_l=g[0], r_h=g[1], delta=g[2], barriers=[b for b, _ in bt],
+                         trap=any(t for _, t in bt), worst=max(b for b, _ in bt)))
     ok = [r for r in rows if not r["trap"]]
-    best = min(ok, key=lambda r: r["worst"]) if ok else None
-    return dict(E_a=E_a, valencies=list(fs), points=points, geometries=len(rows), best=best, rows=rows)
+    ok.sort(key=lambda r: r["worst"])
+    return dict(E_a=E_a, valencies=list(fs), points=points, geometries=len(rows), trap_free=len(ok),
+                best=ok[:5], rows=rows)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--points", type=int, default=41)
     a = ap.parse_args()
-    res = scan(points=a.points)
-    named = {"standard VBC(1.5, 2.0, 0)": (1.5, 2.0, 0.0), "exchange-tuned VBC(1.29, 1.50, 0.30)": (1.29, 1.50, 0.30)}
-    U = profiles(list(named.values()), (1, 2, 3, 4, 5), a.points)
-    res["named"] = {name: [barrier_and_trap(U[k, j]) for j in range(5)] for k, name in enumerate(named)}
+    named = {"standard VBC(1.5, 2.0, 0)": (1.5, 2.0, 0.0),
+             "exchange-tuned VBC(1.29, 1.50, 0.30)": (1.29, 1.50, 0.30)}
+    U, radii = landscapes(list(named.values()), (1, 2, 3, 4, 5), a.points)
+    out = {"named": {name: [barrier_and_trap(U[k, j], radii[k], 1.5) for j in range(5)]
+                     for k, name in enumerate(named)}}
+    res = scan()
     res.pop("rows")
-    print(json.dumps(res), flush=True)
+    out["scan"] = res
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

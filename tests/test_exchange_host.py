@@ -1,32 +1,50 @@
-"""Host logic of the exchange-path analysis (no GPU): path geometry, barrier and trap."""
+"""Host logic of the exchange-landscape analysis (no GPU): geometry, minimax path, barrier
+and trap."""
 import numpy as np
 import pytest
 
 from paper_2609_07842_amd import workloads as W
 
 
-def test_path_geometry():
+def test_positions():
     from paper_2609_07842_amd import exchange as E
     p = W.vbc_params(f=3.0)
-    x0, x1 = E.path_positions(p, 3, 0.0) - E.BOX / 2, E.path_positions(p, 3, 1.0) - E.BOX / 2
-    m, d = 1.25, 2.5
-    # centre, A at the well minimum, B beyond every range; spectators at the minimum on y
-    assert np.allclose(x0[:3], [[0, 0, 0], [m, 0, 0], [-d, 0, 0]])
-    assert np.allclose(x1[:3], [[0, 0, 0], [d, 0, 0], [-m, 0, 0]])
-    assert np.allclose(x0[3:], [[0, m, 0], [0, -m, 0]]) and np.allclose(x0[3:], x1[3:])
+    x = E.positions(p, 3, 1.1, 2.3) - E.BOX / 2
+    assert np.allclose(x, [[0, 0, 0], [1.1, 0, 0], [-2.3, 0, 0], [0, 1.25, 0], [0, -1.25, 0]])
+    r = E.grid_radii(p, 11)
+    assert r[0] == pytest.approx(0.9) and r[-1] == pytest.approx(2.5)
     with pytest.raises(ValueError):
-        E.path_positions(p, 6, 0.5)
+        E.positions(p, 6, 1.0, 1.0)
+
+
+def test_bottleneck_finds_the_pass():
+    from paper_2609_07842_amd.exchange import bottleneck
+    # two wells in opposite corners, a ridge of height 5 with a pass of height 2 at one cell
+    U = np.zeros((9, 9))
+    U[4, :] = 5.0
+    U[4, 6] = 2.0
+    U[0, 0] = U[8, 8] = -1.0
+    assert bottleneck(U, (0, 0), (8, 8)) == 2.0
+    U[4, 6] = 7.0  # no pass lower than the ridge
+    assert bottleneck(U, (0, 0), (8, 8)) == 5.0
+    # a diagonal step counts as a neighbour
+    V = np.full((3, 3), 9.0)
+    V[0, 0] = V[1, 1] = V[2, 2] = 0.0
+    assert bottleneck(V, (0, 0), (2, 2)) == 0.0
 
 
 def test_barrier_and_trap():
     from paper_2609_07842_amd.exchange import barrier_and_trap
-    lam = np.linspace(0, 1, 21)
-    hump = -1.0 + 0.5 * np.sin(np.pi * lam)
-    assert barrier_and_trap(hump) == (pytest.approx(0.5), False)
-    # a dip below the end points inside the path is a trap
-    dip = -1.0 - 0.3 * np.sin(np.pi * lam)
-    b, trap = barrier_and_trap(dip)
-    assert b == pytest.approx(0.0) and trap
-    # a dip between two humps that stays above the start is not a trap
-    two = -1.0 + 0.4 * np.abs(np.sin(2 * np.pi * lam))
-    assert barrier_and_trap(two) == (pytest.approx(0.4, abs=1e-3), False)
+    r = np.linspace(0.9, 2.5, 33)
+    well = lambda q: -2.0 * np.exp(-((q - 1.25) / 0.15) ** 2)
+    A, B = np.meshgrid(r, r, indexing="ij")
+    # a bond only while the other particle is away: any exchange loses the whole well first
+    U = np.where(B >= 1.8, well(A), 0.0) + np.where(A >= 1.8, well(B), 0.0)
+    b, trap = barrier_and_trap(U, r, 1.5)
+    assert not trap and b == pytest.approx(-U.min(), abs=1e-4)  # up to the wells' tails
+    # a channel through the double-bonded corner at half the depth: barrier 1
+    U1 = np.minimum(U, -1.0 * ((A < 1.8) & (B < 1.8)))
+    assert barrier_and_trap(U1, r, 1.5) == (pytest.approx(1.0, abs=1e-9), False)
+    # both bonded deeper than one bond: a trap
+    U2 = np.minimum(U, -3.0 * ((A < 1.4) & (B < 1.4)))
+    assert barrier_and_trap(U2, r, 1.5)[1]

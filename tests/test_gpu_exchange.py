@@ -1,5 +1,5 @@
-"""Energy along the partner-exchange path (Section 4) on the GPU against the oracle: every
-point of the path is one replica of a batched handle."""
+"""Energy landscape of the partner exchange (Section 4) on the GPU against the oracle: every
+grid point is one replica of a batched handle."""
 import numpy as np
 import pytest
 
@@ -11,28 +11,31 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_exchange_path_energies_match_oracle():
+def test_exchange_landscape_energies_match_oracle():
     from paper_2609_07842_amd import exchange as E
     geoms = [(1.5, 2.0, 0.0), (1.29, 1.50, 0.30), (1.35, 1.8, 0.1)]
     fs = (1, 3, 5)
-    lams = np.linspace(0.0, 1.0, 11)
-    U = E.profiles(geoms, fs, points=len(lams))
+    U, radii = E.landscapes(geoms, fs, points=9)
+    rng = np.random.default_rng(0)
     for k, (rl, rh, dl) in enumerate(geoms):
         for j, f in enumerate(fs):
             p = W.vbc_params(E_a=2.0, f=float(f), r_l=rl, r_h=rh, delta=dl)
-            ref = [oracle.evaluate(E.path_positions(p, f, lam), E.BOX, p)["U"] for lam in lams]
-            assert np.allclose(U[k, j], ref, rtol=1e-12, atol=1e-12)
+            for a, b in rng.integers(0, 9, size=(8, 2)):
+                ref = oracle.evaluate(E.positions(p, f, radii[k][a], radii[k][b]), E.BOX, p)["U"]
+                assert U[k, j, a, b] == pytest.approx(ref, rel=1e-12, abs=1e-12)
 
 
 def test_exchange_tuned_geometry_lowers_the_barrier():
-    """The standard geometry must break the old bond before the new one forms (barrier =
-    E_a, the count sees the newcomer first); VBC(1.29, 1.50, 0.30) lowers it at every
-    valency the path covers."""
+    """The standard geometry loses the old bond before the new one forms (barrier ~ E_a:
+    the count sees the newcomer first); VBC(1.29, 1.50, 0.30) lowers the barrier by an
+    order of magnitude at every valency the landscape covers."""
     from paper_2609_07842_amd import exchange as E
     fs = (1, 2, 3, 4, 5)
-    U = E.profiles([(1.5, 2.0, 0.0), (1.29, 1.50, 0.30)], fs, points=41, E_a=2.0)
-    std = [E.barrier_and_trap(U[0, j])[0] for j in range(len(fs))]
-    tuned = [E.barrier_and_trap(U[1, j])[0] for j in range(len(fs))]
-    print(f"[exchange] barriers standard {np.round(std, 3).tolist()} tuned {np.round(tuned, 3).tolist()}", flush=True)
-    assert np.allclose(std, 2.0, atol=1e-9)
-    assert all(t < s - 0.5 for t, s in zip(tuned, std))
+    U, radii = E.landscapes([(1.5, 2.0, 0.0), (1.29, 1.50, 0.30)], fs, points=31, E_a=2.0)
+    std = [E.barrier_and_trap(U[0, j], radii[0], 1.5) for j in range(len(fs))]
+    tuned = [E.barrier_and_trap(U[1, j], radii[1], 1.5) for j in range(len(fs))]
+    print(f"[exchange] standard {[(round(b, 3), t) for b, t in std]}", flush=True)
+    print(f"[exchange] tuned    {[(round(b, 3), t) for b, t in tuned]}", flush=True)
+    assert all(b > 1.8 and not t for b, t in std)
+    assert all(bt < bs / 5 for (bt, _), (bs, _) in zip(tuned, std))
+    assert not tuned[0][1] and not tuned[1][1]  # no trap at the valencies Fig. 7 uses it for
