@@ -10,8 +10,11 @@ d = max(r_a, r_h) + 0.5, beyond every range of the potential.
 * The exchange barrier is the height, above that minimum, of the lowest path between them
   on the grid: the minimax (bottleneck) path, found by adding grid points in order of
   energy until the two states connect.
-* A trap is a grid state with both A and B inside the attraction range that lies below
-  the bonded state: an extra particle bound to an already saturated centre.
+* A trap is a grid state with both A and B well inside the attractive well (closer than
+  m + w / 2, w = (r_a - r_r) / 2: at least about half the well depth each) that lies below
+  the bonded state by more than 1 % of E_a: an extra particle bound to an already saturated
+  centre.  (At the edge of the range, r -> r_a, the newcomer barely interacts and such
+  states are degenerate with the bonded one; they are not traps.)
 
 Every grid point is one replica of a batched handle, so a whole landscape is one force
 evaluation per 1024 points on the GPU.
@@ -110,15 +113,17 @@ def bottleneck(U, src, dst):
     return float("inf")
 
 
-def barrier_and_trap(U, r, r_a):
+def barrier_and_trap(U, r, r_r=1.0, r_a=1.5, E_a=2.0):
     """(barrier above the bonded state, trap present) of one landscape U[r_A, r_B]."""
     far = len(r) - 1
     ia = int(np.argmin(U[:, far]))          # A bonded, B away
     ib = int(np.argmin(U[far, :]))          # B bonded, A away
     u0 = min(U[ia, far], U[far, ib])
     saddle = bottleneck(U, (ia, far), (far, ib))
-    both = (r < r_a)[:, None] & (r < r_a)[None, :]
-    trap = bool(np.any(U[both] < u0 - 1e-9))
+    w = 0.5 * (r_a - r_r)
+    core = r < 0.5 * (r_r + r_a) + 0.5 * w
+    both = core[:, None] & core[None, :]
+    trap = bool(np.any(U[both] < u0 - 0.01 * E_a))
     return saddle - u0, trap
 
 
@@ -130,7 +135,7 @@ def scan(r_l=(1.20, 1.25, 1.29, 1.35, 1.40, 1.45, 1.50), r_h=(1.40, 1.50, 1.60, 
     U, radii = landscapes(geoms, fs, points, E_a)
     rows = []
     for k, g in enumerate(geoms):
-        bt = [barrier_and_trap(U[k, j], radii[k], 1.5) for j in range(len(fs))]
+        bt = [barrier_and_trap(U[k, j], radii[k], E_a=E_a) for j in range(len(fs))]
         rows.append(dict(r_l=g[0], r_h=g[1], delta=g[2], barriers=[b for b, _ in bt],
                          trap=any(t for _, t in bt), worst=max(b for b, _ in bt)))
     ok = [r for r in rows if not r["trap"]]
@@ -146,7 +151,7 @@ def main():
     named = {"standard VBC(1.5, 2.0, 0)": (1.5, 2.0, 0.0),
              "exchange-tuned VBC(1.29, 1.50, 0.30)": (1.29, 1.50, 0.30)}
     U, radii = landscapes(list(named.values()), (1, 2, 3, 4, 5), a.points)
-    out = {"named": {name: [barrier_and_trap(U[k, j], radii[k], 1.5) for j in range(5)]
+    out = {"named": {name: [barrier_and_trap(U[k, j], radii[k]) for j in range(5)]
                      for k, name in enumerate(named)}}
     res = scan()
     res.pop("rows")

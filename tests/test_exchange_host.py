@@ -40,11 +40,30 @@ def test_barrier_and_trap():
     A, B = np.meshgrid(r, r, indexing="ij")
     # a bond only while the other particle is away: any exchange loses the whole well first
     U = np.where(B >= 1.8, well(A), 0.0) + np.where(A >= 1.8, well(B), 0.0)
-    b, trap = barrier_and_trap(U, r, 1.5)
+    b, trap = barrier_and_trap(U, r)
     assert not trap and b == pytest.approx(-U.min(), abs=1e-4)  # up to the wells' tails
     # a channel through the double-bonded corner at half the depth: barrier 1
     U1 = np.minimum(U, -1.0 * ((A < 1.8) & (B < 1.8)))
-    assert barrier_and_trap(U1, r, 1.5) == (pytest.approx(1.0, abs=1e-9), False)
-    # both bonded deeper than one bond: a trap
-    U2 = np.minimum(U, -3.0 * ((A < 1.4) & (B < 1.4)))
-    assert barrier_and_trap(U2, r, 1.5)[1]
+    assert barrier_and_trap(U1, r) == (pytest.approx(1.0, abs=1e-9), False)
+    # both bonded deep in the well, below one bond: a trap
+    U2 = np.minimum(U, -3.0 * ((A < 1.35) & (B < 1.35)))
+    assert barrier_and_trap(U2, r)[1]
+    # lower only with the newcomer at the edge of the range: not a trap
+    U3 = np.minimum(U, -2.005 * ((A > 1.2) & (A < 1.3) & (B > 1.45) & (B < 1.5)))
+    assert not barrier_and_trap(U3, r)[1]
+
+
+def test_trap_appears_when_suppression_comes_late():
+    """With oracle energies: a negative shift delta lets an extra particle bind to a
+    saturated centre (a trap); the exchange-tuned geometry has none."""
+    import oracle
+    from paper_2609_07842_amd import exchange as E
+
+    def land(g, f):
+        p = W.vbc_params(E_a=2.0, f=float(f), r_l=g[0], r_h=g[1], delta=g[2])
+        r = E.grid_radii(p, 21)
+        U = np.array([[oracle.evaluate(E.positions(p, f, a, b), E.BOX, p)["U"] for b in r] for a in r])
+        return E.barrier_and_trap(U, r)
+
+    assert land((1.29, 1.50, -0.6), 1)[1]
+    assert not land((1.29, 1.50, 0.30), 1)[1] and not land((1.29, 1.50, 0.30), 3)[1]
