@@ -127,11 +127,13 @@ def barrier_and_trap(U, r, r_r=1.0, r_a=1.5, E_a=2.0):
     return saddle - u0, trap
 
 
-def scan(r_l=(1.20, 1.25, 1.29, 1.35, 1.40, 1.45, 1.50), r_h=(1.40, 1.50, 1.60, 1.70, 1.80, 1.90, 2.00),
-         delta=(0.0, 0.15, 0.30, 0.45), fs=(1, 2, 3, 4, 5), points=21, E_a=2.0):
+def scan(r_l=(1.20, 1.25, 1.29, 1.35, 1.40, 1.45), r_h=(1.50, 1.60, 1.70, 1.80, 1.90, 2.00),
+         delta=(0.0, 0.15, 0.30, 0.45), fs=(1, 2, 3, 4, 5), points=21, E_a=2.0, r_a=1.5):
     """Barrier of every geometry r_l < r_h of the grid at every valency; the objective is the
-    worst barrier over the valencies among geometries without a trap at any of them."""
-    geoms = [g for g in itertools.product(r_l, r_h, delta) if g[0] < g[1]]
+    worst barrier over the valencies among geometries without a trap at any of them.  The
+    counting range must cover the attraction range (r_h >= r_a): a particle attracted
+    beyond r_h would bind without being counted."""
+    geoms = [g for g in itertools.product(r_l, r_h, delta) if g[0] < g[1] and g[1] >= r_a]
     U, radii = landscapes(geoms, fs, points, E_a)
     rows = []
     for k, g in enumerate(geoms):
