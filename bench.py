@@ -104,6 +104,24 @@ def cpu_baseline(wl, target_s=15.0):
             "seconds": dt}
 
 
+def achievable_copy(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes per second) of torch's copy
+    kernel on 1 GiB buffers: the achievable HBM rate beside the nominal peak."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    a.copy_(b)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        a.copy_(b)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measure_clusters(s, wl, torch, kbar, reps=5):
     """Cluster analysis of the bond graph on the state the timed steps left: one warm call,
     then `reps` calls between HIP events on the launch stream.  Algorithmic bytes per
@@ -304,8 +322,10 @@ def main():
     mean_s = ms / n / 1e3
     nbytes = kernel_bytes(dom, wl.N, main_run["kbar"], "fp32")
     achieved = nbytes / mean_s / 1e9
+    copy_gbs = achievable_copy(torch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "achievable_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                 "traffic": measured_traffic(dom),
                 "bytes_per_launch": nbytes, "mean_launch_us": mean_s * 1e6,
                 "timing": "HIP events around every launch in a second timed region of the same "
