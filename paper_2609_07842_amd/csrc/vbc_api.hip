@@ -76,7 +76,7 @@ struct Caps {
 struct Offsets {
     size_t reps, brick_rep, wl0, wl1, wl_n, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
         bfill, x0, x1, v, Fst, xref, tag, type, lcell, xs, vs, tags, types, lcells, src, inv,
-        smap, wmap, stotal, nl, nn, nd, sA, win, part, flags, step, stats, bevals, bentries,
+        smap, wmap, stotal, nl, nn, nd, sA, wcnt, wlst, part, flags, step, stats, bevals, bentries,
         stamps, stamp_n;
     size_t bytes;
 };
@@ -389,7 +389,8 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
     o.nn = carve(off, sizeof(uint16_t) * S);
     o.nd = carve(off, sizeof(double) * S);
     o.sA = carve(off, (precision == VBC_FP64 ? 16 : 8) * (size_t)S);
-    o.win = carve(off, nb);
+    o.wcnt = carve(off, sizeof(int32_t) * nb);
+    o.wlst = carve(off, sizeof(uint16_t) * S);
     o.part = carve(off, sizeof(double) * 8 * nb);
     o.flags = carve(off, sizeof(uint32_t) * nr);
     o.step = carve(off, sizeof(uint64_t) * nr);
@@ -406,8 +407,8 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
 // per-cell, per-particle and per-replica array of the layout above.
 size_t footprint_bytes(const RepPlan &rp, int precision, int nchunk, int stage_cap)
 {
-    size_t per_slot = 7 * 24 + 5 * 4 + 2 + 16 * (size_t)nchunk + 2 + 8 + (precision == VBC_FP64 ? 16 : 8);
-    size_t per_brick = 4 * 8 + 5 * (size_t)stage_cap + 1 + 64 + 8 + 4;
+    size_t per_slot = 7 * 24 + 5 * 4 + 2 + 16 * (size_t)nchunk + 2 + 2 + 8 + (precision == VBC_FP64 ? 16 : 8);
+    size_t per_brick = 4 * 8 + 5 * (size_t)stage_cap + 4 + 64 + 8 + 4;
     size_t per_cell = 5 * 4;
     return per_slot * (size_t)rp.slots + per_brick * (size_t)rp.R.nbrick +
            per_cell * (size_t)rp.R.ncell + 4 * (size_t)rp.R.n + sizeof(RepDev) + 4 + 8 + 32;
@@ -558,7 +559,8 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     B.nn = at<uint16_t>(d_ws, o.nn);
     B.nd = at<double>(d_ws, o.nd);
     B.sA = at<void>(d_ws, o.sA);
-    B.win = at<uint8_t>(d_ws, o.win);
+    B.wcnt = at<int32_t>(d_ws, o.wcnt);
+    B.wlst = at<uint16_t>(d_ws, o.wlst);
     B.part = at<double>(d_ws, o.part);
     B.flags = at<uint32_t>(d_ws, o.flags);
     B.step = at<uint64_t>(d_ws, o.step);

@@ -100,7 +100,8 @@ struct Buffers {
     uint16_t *nn;            // [nslots] list length
     double *nd;              // [nslots] counts (FP64)
     void *sA;                // [nslots] (s or n, A) as float2 / double2
-    uint8_t *win;            // [nbrick_tot] brick holds a particle inside a switching window
+    int32_t *wcnt;           // [nbrick_tot] own particles inside a switching window (last count pass)
+    uint16_t *wlst;          // [nslots] per brick: those particles (brick-local index), compact
     double *part;            // [nbrick_tot][8] per-brick energy/virial partial sums
     uint32_t *flags;         // [nrep]
     uint64_t *step;          // [nrep] step counter (noise counter)

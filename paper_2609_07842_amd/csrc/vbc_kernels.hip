@@ -418,7 +418,7 @@ __global__ void k_admit(Buffers B, int r)
         B.bcnt[1][b] = 0;
         B.bfill[b] = 0;
         B.stotal[b] = 0;
-        B.win[b] = 0;
+        B.wcnt[b] = 0;
         for (int k = 0; k < 8; ++k) B.part[(size_t)b * 8 + k] = 0.0;
         B.bevals[b] = 0ull;
         B.bentries[b] = 0u;
@@ -996,7 +996,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     using R2 = typename V2<Real>::t;
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
-    __shared__ int any_win;
+    __shared__ int nwin;  // own particles inside a switching window
     __shared__ unsigned long long ev_sum;
     __shared__ PairR<Real> pt[MAXT * MAXT];
     int b, r;
@@ -1008,7 +1008,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     const int64_t S_ = P.nslots;
     load_pairs<Real>(R, pt);
     if (threadIdx.x == 0) {
-        any_win = 0;
+        nwin = 0;
         ev_sum = 0ull;
         pass_header(R, B, b, lb, P.stage_cap, S);
     }
@@ -1022,7 +1022,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         }
         if (threadIdx.x == 0) {
             atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
-            B.win[b] = 0;
+            B.wcnt[b] = 0;
         }
         return;
     }
@@ -1039,7 +1039,6 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     const double wx1 = R.pair[0].x1, wx2 = R.pair[0].x2;
     const bool watt = R.pair[0].attract;
     const int64_t o_off = R.o_off;
-    bool win = false;
     unsigned long long evals = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
@@ -1081,6 +1080,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         });
         evals += (unsigned long long)inside;
         B.nd[i] = n;
+        bool win = false;
         if (MULTI) {
             // the switching factor depends on the pair: keep the count itself
             sA[i] = R2{(Real)n, Real(0)};
@@ -1090,18 +1090,19 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
             }
         } else {
             sA[i] = R2{(Real)omega_d64(n, wx1, wx2), Real(0)};
-            if (watt && n > wx1 && n < wx2) win = true;
+            win = watt && n > wx1 && n < wx2;
         }
+        // the dU/dn pass visits only these: list them compactly in the brick's slots
+        if (win) B.wlst[S.base + atomicAdd(&nwin, 1)] = (uint16_t)t;
         if (n_out) n_out[o_off + B.tag[i]] = n;
     }
-    if (win) any_win = 1;
     if (STATS) {
         evals = wave_sum(evals);
         if ((threadIdx.x % VBC_WAVE) == 0 && evals) atomicAdd(&ev_sum, evals);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        B.win[b] = (uint8_t)any_win;
+        B.wcnt[b] = nwin;
         if (STATS) B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
         if (lb == 0) {
             if (STATS) B.stats[4 * r + 3] += 1ull;
@@ -1116,74 +1117,124 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
 // pass 2a: dU/dn for particles inside a switching window
 // ---------------------------------------------------------------------------
 
+// Bricks per workgroup of the dU/dn pass: one wave each.
+constexpr int EMBED_WAVES = 4;
+
+// Like resolve_brick, for workgroups that take `per` consecutive bricks, one per wave w:
+// units of `per` bricks are dealt to the XCDs in contiguous runs.
+__device__ __forceinline__ bool resolve_brick_of_wave(const Launch &P, const Buffers &B, int per, int w,
+                                                      int &b, int &r)
+{
+    const int g = blockIdx.x, j = g >> 3;
+    const int T = P.list < 0 ? P.nb_launch : B.wl_n[P.list];
+    const int U = (T + per - 1) / per;
+    const int chunk = (U + 7) >> 3;
+    const int k = (g & 7) * chunk + j;
+    if (j >= chunk || k >= U) return false;
+    const int kb = k * per + w;
+    if (kb >= T) return false;
+    b = P.list < 0 ? P.b_lo + kb : B.wl[P.list][kb];
+    r = B.brick_rep[b];
+    return r >= 0;
+}
+
+// One wave per brick over the particles that the count pass listed as inside a switching
+// window (most bricks hold a handful or none); no workgroup-wide synchronisation.
 template <class Real, bool MULTI>
 __global__ void k_embed(Buffers B, Launch P, int cur)
 {
     using R2 = typename V2<Real>::t;
-    extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ StageHdr S;
-    __shared__ PairR<Real> pt[MAXT * MAXT];
-    __shared__ int nw;
-    int *wl = (int *)smem;  // [bcap] own particles inside a switching window
+    __shared__ PairR<Real> ptab[EMBED_WAVES][MAXT * MAXT];
+    const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
     int b, r;
-    if (!resolve_brick(P, B, b, r) || !B.win[b]) return;
+    if (!resolve_brick_of_wave(P, B, EMBED_WAVES, wv, b, r)) return;
+    const int nw = B.wcnt[b];
+    if (nw == 0 || B.stotal[b] > P.stage_cap) return;  // nothing in a window, or an overflowed brick
     const RepDev &R = B.reps[r];
-    int lb = b - R.b_off;
+    const int lb = b - R.b_off;
     const int64_t S_ = P.nslots;
-    load_pairs<Real>(R, pt);
-    if (threadIdx.x == 0) {
-        pass_header(R, B, b, lb, P.stage_cap, S);
-        nw = 0;
-    }
-    __syncthreads();
-    if (S.overflow) return;
-    // 1. collect the brick's particles whose count lies inside a switching window
-    for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
-        double n_i = B.nd[S.base + t];
-        bool any = false;
-        if (MULTI) {
-            int ti = B.type[S.base + t];
-            for (int u = 0; u < R.ntypes; ++u) {
-                const PairDev &pd = R.pair[ti * MAXT + u];
-                if (pd.attract && n_i > pd.x1 && n_i < pd.x2) any = true;
-            }
-        } else {
-            any = R.pair[0].attract && n_i > R.pair[0].x1 && n_i < R.pair[0].x2;
+    const int64_t base = R.p_off + (int64_t)lb * R.bcap;
+    PairR<Real> *pt = ptab[wv];
+    if (MULTI) {
+        const int nt = R.ntypes;
+        if (lane < nt * nt) {
+            const int a = lane / nt, c = lane % nt;
+            pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
         }
-        if (any) wl[atomicAdd(&nw, 1)] = t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
-    // 2. eight lanes per window particle, one entry of each list chunk per lane; neighbours
-    //    are gathered from global memory through the brick's staging map
+    // eight lanes per window particle, one entry of each list chunk per lane; neighbours
+    // are gathered from global memory through the brick's staging map
     R2 *sA = (R2 *)B.sA;
     const double *X = B.x[cur];
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
     const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
-    const PairR<Real> p0 = pt[0];
-    const int e = threadIdx.x % CHUNK;
-    const int g = threadIdx.x / CHUNK, ng = blockDim.x / CHUNK;
+    const PairR<Real> p0 = pair_r<Real>(R.pair[0], R.rc2);
+    const int e = lane % CHUNK;
+    const int g = lane / CHUNK, ng = VBC_WAVE / CHUNK;
     for (int k = g; k < nw; k += ng) {
-        int t = wl[k];
-        int64_t i = S.base + t;
+        int t = B.wlst[base + k];
+        int64_t i = base + t;
         double n_i = B.nd[i];
         int ti = MULTI ? B.type[i] : 0;
         const double xi0 = X[i], xi1 = X[S_ + i], xi2 = X[2 * S_ + i];
         int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
-        for (int c = 0; c < nch; ++c) {
-            uint4 q = B.nl[(size_t)c * S_ + i];
-            uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
-            int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
-            if (MULTI && R.excl_span > 0) {
-                if (u & 0x8000) continue;  // excluded pair: no attraction between them
+        if (!MULTI) {
+            // four chunks at a time in phases (chunk words, staging map, positions, terms)
+            // with no branch between the loads, so that the gathers of all four go out together;
+            // rows past the list and the padding slot read valid memory and are masked
+            for (int c0 = 0; c0 < nch; c0 += 4) {
+                int uj[4], sj[4], wj[4];
+                bool vj[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = min(c0 + j, nch - 1);
+                    const uint4 q = B.nl[(size_t)c * S_ + i];
+                    const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
+                    const int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+                    vj[j] = c0 + j < nch && u != P.stage_cap;
+                    uj[j] = vj[j] ? u : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sj[j] = sm[uj[j]];
+                    wj[j] = wm[uj[j]];
+                }
+                double xj[4][3];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    for (int a = 0; a < 3; ++a) xj[j][a] = X[a * S_ + sj[j]];
+                Real sjv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sjv[j] = sA[sj[j]].x;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    Real dx = (Real)(xi0 - (xj[j][0] + R.L[0] * (double)unpack_w(wj[j], 0)));
+                    Real dy = (Real)(xi1 - (xj[j][1] + R.L[1] * (double)unpack_w(wj[j], 1)));
+                    Real dz = (Real)(xi2 - (xj[j][2] + R.L[2] * (double)unpack_w(wj[j], 2)));
+                    Real r2 = dx * dx + dy * dy + dz * dz;
+                    Real uu = (sqrt_r(r2) - p0.m) * p0.inv_w;
+                    Real qq = Real(1) - uu * uu;
+                    if (vj[j] && qq > Real(0)) acc += (double)(sjv[j] * (-p0.E_a * qq * qq));
+                }
             }
-            if (u == P.stage_cap) continue;  // padding
-            int src = sm[u], w = wm[u];
-            Real dx = (Real)(xi0 - (X[src] + R.L[0] * (double)unpack_w(w, 0)));
-            Real dy = (Real)(xi1 - (X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)));
-            Real dz = (Real)(xi2 - (X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)));
-            Real r2 = dx * dx + dy * dy + dz * dz;
-            if (MULTI) {
+        } else {
+            for (int c = 0; c < nch; ++c) {
+                uint4 q = B.nl[(size_t)c * S_ + i];
+                uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
+                int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+                if (R.excl_span > 0) {
+                    if (u & 0x8000) continue;  // excluded pair: no attraction between them
+                }
+                if (u == P.stage_cap) continue;  // padding
+                int src = sm[u], w = wm[u];
+                Real dx = (Real)(xi0 - (X[src] + R.L[0] * (double)unpack_w(w, 0)));
+                Real dy = (Real)(xi1 - (X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)));
+                Real dz = (Real)(xi2 - (X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)));
+                Real r2 = dx * dx + dy * dy + dz * dz;
                 int tj = B.type[src];
                 const PairR<Real> &q2 = pt[ti * MAXT + tj];
                 if (!q2.attract) continue;
@@ -1194,11 +1245,6 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
                 double sdi = omega_dd64(n_i, pd.x1, pd.x2);
                 Real sj = omega_r<Real>(sA[src].x, q2.x1, q2.x2);
                 acc += sdi * (double)(sj * (-q2.E_a * qq * qq));
-            } else {
-                Real uu = (sqrt_r(r2) - p0.m) * p0.inv_w;
-                Real qq = Real(1) - uu * uu;
-                if (!(qq > Real(0))) continue;
-                acc += (double)(sA[src].x * (-p0.E_a * qq * qq));
             }
         }
         // fixed-order reduction over the eight lanes of the group
@@ -2165,7 +2211,7 @@ size_t lds_bytes_count(const Launch &P)
 {
     return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : 16);
 }
-size_t lds_bytes_embed(const Launch &P) { return (size_t)P.bcap_max * sizeof(int); }
+size_t lds_bytes_embed(const Launch &P) { (void)P; return 0; }
 // bond tests (observables, clusters): FP32 staging, then the slots or the brick's forest
 size_t lds_bytes_bonds(const Launch &P)
 {
@@ -2275,10 +2321,10 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
 
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    unsigned g = brick_grid(P.nb_launch);
+    unsigned g = brick_grid((P.nb_launch + EMBED_WAVES - 1) / EMBED_WAVES);
     bool multi = P.multi != 0;
-    const int bs = 256;
-    size_t lds = lds_bytes_embed(P);
+    const int bs = EMBED_WAVES * VBC_WAVE;
+    size_t lds = 0;
     if (P.precision == VBC_FP64) {
         if (multi) k_embed<double, true><<<g, bs, lds, s>>>(B, P, cur);
         else k_embed<double, false><<<g, bs, lds, s>>>(B, P, cur);
