@@ -330,6 +330,30 @@ __device__ __forceinline__ void stage_map(const Buffers &B, int b, int stage_cap
     for (int t = threadIdx.x; t < S.total; t += blockDim.x) fn(t, sm[t], (int)wm[t]);
 }
 
+// stage_map with four staged particles per thread at a time: the map reads of all four go
+// out first, then fn(staged_slot, source_slot, packed_shift, valid) for each; fn must do
+// its own loads unconditionally (the indices are clamped into the staging) and guard only
+// its stores with valid, so that the gathers of the four overlap.
+template <class F>
+__device__ __forceinline__ void stage_map4(const Buffers &B, int b, int stage_cap, const StageHdr &S,
+                                           F &&fn)
+{
+    const int32_t *sm = B.smap + (size_t)b * stage_cap;
+    const uint8_t *wm = B.wmap + (size_t)b * stage_cap;
+    const int nt = blockDim.x, last = S.total - 1;
+    for (int t0 = threadIdx.x; t0 < S.total; t0 += 4 * nt) {
+        int src[4], w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = min(t0 + j * nt, last);
+            src[j] = sm[t];
+            w[j] = (int)wm[t];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fn(t0 + j * nt, src[j], w[j], t0 + j * nt < S.total);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // state in / out, flags
 // ---------------------------------------------------------------------------
@@ -1027,8 +1051,9 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         return;
     }
     const double *X = B.x[cur];
-    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
-        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
+    stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
+        const R4 p = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
+        if (ok) spos[t] = p;
     });
     if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<R4>();
     __syncthreads();
@@ -1317,11 +1342,14 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     }
     const double *X = B.x[cur];
     const Real cc0 = pt[0].c_c;
-    stage_map(B, b, P.stage_cap, S, [&](int t, int src, int w) {
-        spos[t] = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
+    stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
+        const R4 p = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
         R2 sa = sA[src];
         if (!MULTI) sa.y *= cc0;  // one type: the chain-rule term needs only c_c A
-        ssa[t] = sa;
+        if (ok) {
+            spos[t] = p;
+            ssa[t] = sa;
+        }
     });
     if (threadIdx.x == 0) {
         spos[P.stage_cap] = dummy_pos<R4>();
