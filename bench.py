@@ -41,19 +41,21 @@ METRIC = "VBC pair evals/s + timesteps/s at N=1M (frac. HBM roofline); p99 step 
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(kind: str, N: int, kbar: float, precision: str) -> float:
+def kernel_bytes(kind: str, N: int, kbar: float, precision: str, ntypes: int = 1) -> float:
     """Algorithmic HBM bytes of one launch of a kernel class, for the chosen layout.
 
     Every datum a launch needs is counted once: list entries are 2 bytes, counts per
-    particle 2 bytes, positions/velocities/reference positions FP64 SoA; halo copies
-    staged by several workgroups are cache re-reads, not algorithmic traffic."""
+    particle 2 bytes, positions/velocities/reference positions FP64 SoA, the type (4 bytes)
+    only with several types; halo copies staged by several workgroups are cache re-reads,
+    not algorithmic traffic."""
     sa = 8 if precision == "fp32" else 16
+    ty = 4 if ntypes > 1 else 0
     if kind == "count":
-        # list + nn + x + type  ->  n (FP64) + (s, A)
-        return N * (2 * kbar + 2 + 24 + 4 + 8 + sa)
+        # list + nn + x (+ type)  ->  n (FP64) + (s, A)
+        return N * (2 * kbar + 2 + 24 + ty + 8 + sa)
     if kind == "force":
-        # list + nn + x + type + (s, A) + tag + v (r/w) + x_next (w) + x_ref (r)
-        return N * (2 * kbar + 2 + 24 + 4 + sa + 4 + 48 + 24 + 24)
+        # list + nn + x (+ type) + (s, A) + tag + v (r/w) + x_next (w) + x_ref (r)
+        return N * (2 * kbar + 2 + 24 + ty + sa + 4 + 48 + 24 + 24)
     if kind == "build":
         # x, v, tag, type read and gathered, cell tables, list written
         return N * (48 + 8 + 4 * 6 + 48 + 8 + 24 + 2 * kbar + 2)

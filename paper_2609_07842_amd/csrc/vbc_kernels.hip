@@ -1052,7 +1052,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     }
     const double *X = B.x[cur];
     stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
-        const R4 p = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
+        const R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
         if (ok) spos[t] = p;
     });
     if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<R4>();
@@ -1324,8 +1324,12 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
+    // staged per particle: position and, with one type, the switching factor s in .w plus
+    // c_c A in a separate array (20 bytes in FP32); with several types the type in .w and
+    // (s or n, A) beside it
     R4 *spos = (R4 *)smem;
     R2 *ssa = (R2 *)(spos + P.stage_cap + 1);
+    Real *scA = (Real *)(spos + P.stage_cap + 1);
     const int64_t S_ = P.nslots;
     const int64_t ntot = P.ntot;
     load_pairs<Real>(R, pt);
@@ -1343,17 +1347,19 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     const double *X = B.x[cur];
     const Real cc0 = pt[0].c_c;
     stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
-        const R4 p = local_pos<Real>(R, S, X, S_, src, w, B.type[src]);
-        R2 sa = sA[src];
-        if (!MULTI) sa.y *= cc0;  // one type: the chain-rule term needs only c_c A
+        R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
+        const R2 sa = sA[src];
+        if (!MULTI) p.w = sa.x;
         if (ok) {
             spos[t] = p;
-            ssa[t] = sa;
+            if (MULTI) ssa[t] = sa;
+            else scA[t] = sa.y * cc0;  // one type: the chain-rule term needs only c_c A
         }
     });
     if (threadIdx.x == 0) {
         spos[P.stage_cap] = dummy_pos<R4>();
-        ssa[P.stage_cap] = R2{Real(0), Real(0)};
+        if (MULTI) ssa[P.stage_cap] = R2{Real(0), Real(0)};
+        else scA[P.stage_cap] = Real(0);
     }
     __syncthreads();
 
@@ -1370,7 +1376,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
         R4 pi = spos[t];
-        R2 sai = ssa[t];
+        const R2 sai = MULTI ? ssa[t] : R2{pi.w, scA[t]};
         int ti = MULTI ? (int)pi.w : 0;
         const Real cai = p0.c_a * sai.x;
         Real fx = 0, fy = 0, fz = 0, ei = 0;
@@ -1415,7 +1421,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 // branch-free: beyond every cutoff (and for the padding slot) all three terms
                 // vanish through the clamps.  phi/r = min(c_r + k_r r^2, 0)
                 //   + [ c_a s_i s_j u_a q_a + (c_c A_i + c_c A_j) u_c (1 - u_c^2) ] / r
-                R2 saj = ssa[u];
+                const Real sj = pj.w, cAj = scA[u];
                 Real rinv = rsqrt_r(r2 > Real(1e-30) ? r2 : Real(1e-30));
                 Real rr = r2 * rinv;
                 Real pr = fmin(fma(r2, p0.k_r, p0.c_r), Real(0));
@@ -1423,11 +1429,11 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 Real qq = fmax(fma(-uu, uu, Real(1)), Real(0));
                 Real uc = clamp01(fma(rr, p0.inv_dw, p0.nrl_dw));
                 Real g = uc * fma(-uc, uc, Real(1));
-                Real t = fma(sai.y + saj.y, g, cai * saj.x * uu * qq);
+                Real t = fma(sai.y + cAj, g, cai * sj * uu * qq);
                 phr = fma(t, rinv, pr);
                 if (THERMO) {
                     Real tc = fmax(fma(-r2, p0.inv_rr2, Real(1)), Real(0));
-                    ep = p0.E_r * tc * tc - p0.E_a * (sai.x * saj.x) * qq * qq;
+                    ep = p0.E_r * tc * tc - p0.E_a * (sai.x * sj) * qq * qq;
                 }
             }
             fx -= phr * dx;
@@ -2248,7 +2254,8 @@ size_t lds_bytes_bonds(const Launch &P)
 }
 size_t lds_bytes_force(const Launch &P)
 {
-    return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 48 : 24);
+    const size_t real = P.precision == VBC_FP64 ? 8 : 4;
+    return (size_t)(P.stage_cap + 1) * real * (P.multi ? 6 : 5);
 }
 
 hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
