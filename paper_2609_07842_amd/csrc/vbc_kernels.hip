@@ -60,7 +60,7 @@ __device__ __forceinline__ double clamp01(double u) { return fmin(fmax(u, 0.0), 
 // [b_lo, b_lo + nb_launch) (P.list < 0: all bricks, or one replica's) or the entries of
 // work list P.list, which the step computes on the GPU.  Returns false for a workgroup
 // with nothing to do (padding, or a free brick).
-__device__ __forceinline__ bool resolve_brick(const Launch &P, const Buffers &B, int &b, int &r)
+__device__ __forceinline__ bool brick_of_block(const Launch &P, const Buffers &B, int &b)
 {
     const int g = blockIdx.x, j = g >> 3;
     const int T = P.list < 0 ? P.nb_launch : B.wl_n[P.list];
@@ -68,6 +68,12 @@ __device__ __forceinline__ bool resolve_brick(const Launch &P, const Buffers &B,
     const int k = (g & 7) * chunk + j;
     if (j >= chunk || k >= T) return false;
     b = P.list < 0 ? P.b_lo + k : B.wl[P.list][k];
+    return true;
+}
+
+__device__ __forceinline__ bool resolve_brick(const Launch &P, const Buffers &B, int &b, int &r)
+{
+    if (!brick_of_block(P, B, b)) return false;
     r = B.brick_rep[b];
     return r >= 0;
 }
@@ -334,20 +340,52 @@ __device__ __forceinline__ void stage_map(const Buffers &B, int b, int stage_cap
 // out first, then fn(staged_slot, source_slot, packed_shift, valid) for each; fn must do
 // its own loads unconditionally (the indices are clamped into the staging) and guard only
 // its stores with valid, so that the gathers of the four overlap.
+//
+// The map entries of the first four (threadIdx.x + j blockDim.x) are read by map_prefetch
+// as soon as the brick is known, before its header: their latency then overlaps the
+// header's, and the gathers can go out right after the header's barrier.  Entries past the
+// staged count are stale but valid slot indices (the map is cleared at creation and only
+// ever holds slots), and their stores are not made.
+struct MapFirst {
+    int src[4], w[4];
+};
+
+__device__ __forceinline__ MapFirst map_prefetch(const Buffers &B, int b, int stage_cap)
+{
+    const int32_t *sm = B.smap + (size_t)b * stage_cap;
+    const uint8_t *wm = B.wmap + (size_t)b * stage_cap;
+    MapFirst m;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int t = min((int)(threadIdx.x + j * blockDim.x), stage_cap - 1);
+        m.src[j] = sm[t];
+        m.w[j] = (int)wm[t];
+    }
+    return m;
+}
+
 template <class F>
 __device__ __forceinline__ void stage_map4(const Buffers &B, int b, int stage_cap, const StageHdr &S,
-                                           F &&fn)
+                                           const MapFirst &first, F &&fn)
 {
     const int32_t *sm = B.smap + (size_t)b * stage_cap;
     const uint8_t *wm = B.wmap + (size_t)b * stage_cap;
     const int nt = blockDim.x, last = S.total - 1;
     for (int t0 = threadIdx.x; t0 < S.total; t0 += 4 * nt) {
         int src[4], w[4];
+        if (t0 == (int)threadIdx.x) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int t = min(t0 + j * nt, last);
-            src[j] = sm[t];
-            w[j] = (int)wm[t];
+            for (int j = 0; j < 4; ++j) {
+                src[j] = first.src[j];
+                w[j] = first.w[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = min(t0 + j * nt, last);
+                src[j] = sm[t];
+                w[j] = (int)wm[t];
+            }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) fn(t0 + j * nt, src[j], w[j], t0 + j * nt < S.total);
@@ -1048,12 +1086,14 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
     extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ StageHdr S;
     __shared__ int nwin;  // own particles inside a switching window
     __shared__ unsigned long long ev_sum;
     __shared__ PairR<Real> pt[MAXT * MAXT];
-    int b, r;
-    if (!resolve_brick(P, B, b, r)) return;
+    int b;
+    if (!brick_of_block(P, B, b)) return;
+    const MapFirst mf = map_prefetch(B, b, P.stage_cap);
+    const int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
@@ -1063,9 +1103,11 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     if (threadIdx.x == 0) {
         nwin = 0;
         ev_sum = 0ull;
-        pass_header(R, B, b, lb, P.stage_cap, S);
     }
-    __syncthreads();
+    // every thread reads the header itself (uniform values), so that the staging gathers
+    // need not wait for a barrier; the staging barrier orders pt, nwin and ev_sum
+    StageHdr S;
+    pass_header(R, B, b, lb, P.stage_cap, S);
     R2 *sA = (R2 *)B.sA;
     if (S.overflow) {
         for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
@@ -1080,7 +1122,7 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         return;
     }
     const double *X = B.x[cur];
-    stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
+    stage_map4(B, b, P.stage_cap, S, mf, [&](int t, int src, int w, bool ok) {
         const R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
         if (ok) spos[t] = p;
     });
@@ -1349,8 +1391,11 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ double red[8][1024 / VBC_WAVE];
     __shared__ int moved;
-    int b, r;
-    if (!resolve_brick(P, B, b, r)) return;
+    int b;
+    if (!brick_of_block(P, B, b)) return;
+    const MapFirst mf = map_prefetch(B, b, P.stage_cap);
+    const int r = B.brick_rep[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     // staged per particle: position and, with one type, the switching factor s in .w plus
@@ -1375,7 +1420,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     }
     const double *X = B.x[cur];
     const Real cc0 = pt[0].c_c;
-    stage_map4(B, b, P.stage_cap, S, [&](int t, int src, int w, bool ok) {
+    stage_map4(B, b, P.stage_cap, S, mf, [&](int t, int src, int w, bool ok) {
         R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
         const R2 sa = sA[src];
         if (!MULTI) p.w = sa.x;
