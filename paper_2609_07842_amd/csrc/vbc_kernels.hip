@@ -1218,8 +1218,7 @@ constexpr int EMBED_WAVES = 4;
 
 // Like resolve_brick, for workgroups that take `per` consecutive bricks, one per wave w:
 // units of `per` bricks are dealt to the XCDs in contiguous runs.
-__device__ __forceinline__ bool resolve_brick_of_wave(const Launch &P, const Buffers &B, int per, int w,
-                                                      int &b, int &r)
+__device__ __forceinline__ bool brick_of_wave(const Launch &P, const Buffers &B, int per, int w, int &b)
 {
     const int g = blockIdx.x, j = g >> 3;
     const int T = P.list < 0 ? P.nb_launch : B.wl_n[P.list];
@@ -1230,8 +1229,7 @@ __device__ __forceinline__ bool resolve_brick_of_wave(const Launch &P, const Buf
     const int kb = k * per + w;
     if (kb >= T) return false;
     b = P.list < 0 ? P.b_lo + kb : B.wl[P.list][kb];
-    r = B.brick_rep[b];
-    return r >= 0;
+    return true;
 }
 
 // One wave per brick over the particles that the count pass listed as inside a switching
@@ -1242,14 +1240,22 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     using R2 = typename V2<Real>::t;
     __shared__ PairR<Real> ptab[EMBED_WAVES][MAXT * MAXT];
     const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
-    int b, r;
-    if (!resolve_brick_of_wave(P, B, EMBED_WAVES, wv, b, r)) return;
+    int b;
+    if (!brick_of_wave(P, B, EMBED_WAVES, wv, b)) return;
+    // the brick's owner, window count and staged count read together, then the replica
+    // descriptor and the first window entry before the tests (valid memory either way), so
+    // that the chain of dependent reads stays short
+    const int r = B.brick_rep[b];
     const int nw = B.wcnt[b];
-    if (nw == 0 || B.stotal[b] > P.stage_cap) return;  // nothing in a window, or an overflowed brick
+    const int tot = B.stotal[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     const int lb = b - R.b_off;
     const int64_t S_ = P.nslots;
     const int64_t base = R.p_off + (int64_t)lb * R.bcap;
+    const int g = lane / CHUNK, ng = VBC_WAVE / CHUNK;
+    const int t_first = B.wlst[base + g];
+    if (nw == 0 || tot > P.stage_cap) return;  // nothing in a window, or an overflowed brick
     PairR<Real> *pt = ptab[wv];
     if (MULTI) {
         const int nt = R.ntypes;
@@ -1269,9 +1275,8 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
     const PairR<Real> p0 = pair_r<Real>(R.pair[0], R.rc2);
     const int e = lane % CHUNK;
-    const int g = lane / CHUNK, ng = VBC_WAVE / CHUNK;
     for (int k = g; k < nw; k += ng) {
-        int t = B.wlst[base + k];
+        int t = k == g ? t_first : B.wlst[base + k];
         int64_t i = base + t;
         double n_i = B.nd[i];
         int ti = MULTI ? B.type[i] : 0;
@@ -1281,14 +1286,19 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
         if (!MULTI) {
             // four chunks at a time in phases (chunk words, staging map, positions, terms)
             // with no branch between the loads, so that the gathers of all four go out together;
-            // rows past the list and the padding slot read valid memory and are masked
+            // rows past the list and the padding slot read valid memory and are masked.  The
+            // first four rows are read before the list length arrives (rows below nchunk exist
+            // for every slot).
+            uint4 qf[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qf[j] = B.nl[(size_t)min(j, P.nchunk - 1) * S_ + i];
             for (int c0 = 0; c0 < nch; c0 += 4) {
                 int uj[4], sj[4], wj[4];
                 bool vj[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int c = min(c0 + j, nch - 1);
-                    const uint4 q = B.nl[(size_t)c * S_ + i];
+                    const int c = min(c0 + j, P.nchunk - 1);
+                    const uint4 q = c0 == 0 ? qf[j] : B.nl[(size_t)c * S_ + i];
                     const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
                     const int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
                     vj[j] = c0 + j < nch && u != P.stage_cap;
