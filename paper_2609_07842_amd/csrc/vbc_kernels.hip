@@ -1397,7 +1397,6 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
     extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ StageHdr S;
     __shared__ PairR<Real> pt[MAXT * MAXT];
     __shared__ double red[8][1024 / VBC_WAVE];
     __shared__ int moved;
@@ -1417,11 +1416,11 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     const int64_t S_ = P.nslots;
     const int64_t ntot = P.ntot;
     load_pairs<Real>(R, pt);
-    if (threadIdx.x == 0) {
-        moved = 0;
-        pass_header(R, B, b, lb, P.stage_cap, S);
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) moved = 0;
+    // every thread reads the header itself (as in the count pass); the staging barrier
+    // orders pt and moved
+    StageHdr S;
+    pass_header(R, B, b, lb, P.stage_cap, S);
     const R2 *sA = (const R2 *)B.sA;
     if (S.overflow) {
         if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
@@ -1429,7 +1428,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         return;
     }
     const double *X = B.x[cur];
-    const Real cc0 = pt[0].c_c;
+    const Real cc0 = pair_r<Real>(R.pair[0], R.rc2).c_c;
     stage_map4(B, b, P.stage_cap, S, mf, [&](int t, int src, int w, bool ok) {
         R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
         const R2 sa = sA[src];
