@@ -721,10 +721,14 @@ __global__ void k_gsort(Buffers B, Launch P, int cur)
 __global__ void k_resort(Buffers B, Launch P, int cur)
 {
     extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ StageHdr S;
+    __shared__ StageHdr Ssh;
     __shared__ int nmem_s;
-    int b, r;
-    if (!resolve_brick(P, B, b, r)) return;
+    int b;
+    if (!brick_of_block(P, B, b)) return;
+    const MapFirst mf = map_prefetch(B, b, P.stage_cap);
+    const int r = B.brick_rep[b];
+    const int tot = B.stotal[b];
+    if (r < 0) return;
     const RepDev &R = B.reps[r];
     uint32_t fl = B.flags[r];
     if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
@@ -732,8 +736,19 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs Q = carve_tabs(smem, nh_cap);
     SortTabs T = carve_sort(after_tabs(smem, nh_cap), P.bcap_max, P.ncb_max);
-    stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], S, Q,
-                 1 << 30);
+    // the candidates (the brick and its one-cell halo in the live layout) are exactly the
+    // particles the last list build staged: read them through its staging map (header in
+    // every thread, no cell-table walk); after an overflowed build, walk the cell tables
+    const bool use_map = tot <= P.stage_cap;
+    StageHdr S;
+    if (use_map) {
+        pass_header(R, B, b, lb, P.stage_cap, S);
+        S.rank0 = B.brick_rank0[b];
+    } else {
+        stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[0], B.ccnt[0], B.bcnt[0], Ssh, Q,
+                     1 << 30);
+        S = Ssh;
+    }
     for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
         T.hist[lc] = 0;
         T.fill[lc] = 0;
@@ -742,20 +757,23 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     __syncthreads();
     const int64_t S_ = P.nslots;
     const int bcap = R.bcap;
-    stage_copy(S, Q, [&](int t, int src, int w) {
+    auto member = [&](int src, bool ok) {
         double xw[3];
         for (int a = 0; a < 3; ++a) xw[a] = wrap1(B.x[cur][a * S_ + src], R.L[a]);
+        const int tg = B.tag[src];
         int lc = local_cell(R, S, xw);
-        if (lc >= 0) {
+        if (ok && lc >= 0) {
             int m = atomicAdd(&nmem_s, 1);
             if (m < bcap) {
                 T.m_src[m] = src;
-                T.m_tag[m] = B.tag[src];
+                T.m_tag[m] = tg;
                 T.m_lc[m] = lc;
                 atomicAdd(&T.hist[lc], 1);
             }
         }
-    });
+    };
+    if (use_map) stage_map4(B, b, P.stage_cap, S, mf, [&](int t, int src, int w, bool ok) { member(src, ok); });
+    else stage_copy(S, Q, [&](int t, int src, int w) { member(src, true); });
     __syncthreads();
     int nmem = nmem_s;
     if (nmem > bcap) {
