@@ -118,6 +118,24 @@ def test_stage_capacity_overflow_reported():
     assert st == vbc.VBC_ERR_CAPACITY
 
 
+def test_resort_after_overflowed_build_keeps_every_particle():
+    """A re-sort after a list build that overflowed the staging capacity cannot read its
+    candidates through that build's staging map and walks the cell tables instead: every
+    particle keeps its position (read back unchanged) and the overflow stays reported."""
+    vbc = _vbc()
+    N = 3000
+    L = W.box_length(N, 0.5)
+    x = W.uniform_positions(N, L, 1)
+    s = vbc.System(vbc.replica(N, L, W.vbc_params()), precision="fp32", stage_cap=256)
+    s.set_state(x)
+    s.build_nlist()  # the full build from caller order: overflows
+    s.build_nlist()  # an incremental build: re-sort, then list
+    st, flags = s.check(raise_on_error=False)
+    assert st == vbc.VBC_ERR_CAPACITY
+    xs, _ = s.get_state()
+    np.testing.assert_array_equal(xs.cpu().numpy(), x)
+
+
 def test_lost_particle_reported():
     vbc = _vbc()
     N = 2000
