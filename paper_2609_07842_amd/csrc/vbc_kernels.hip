@@ -1254,49 +1254,27 @@ __device__ __forceinline__ bool brick_of_wave(const Launch &P, const Buffers &B,
 
 // One wave per brick over the particles that the count pass listed as inside a switching
 // window (most bricks hold a handful or none); no workgroup-wide synchronisation.
-template <class Real, bool MULTI>
-__global__ void k_embed(Buffers B, Launch P, int cur)
+// dU/dn of the window particles of brick b (one wave; see k_embed).  t_first: the first
+// particle of this lane's group if already read, else -1.
+template <int LPP, class Real, bool MULTI>
+__device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, const RepDev &R,
+                                            const PairR<Real> *pt, int b, int64_t base, int nw,
+                                            int lane, int t_first, int cur)
 {
+    // LPP lanes per window particle, EP entries of each list chunk per lane; neighbours are
+    // gathered from global memory through the brick's staging map
     using R2 = typename V2<Real>::t;
-    __shared__ PairR<Real> ptab[EMBED_WAVES][MAXT * MAXT];
-    const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
-    int b;
-    if (!brick_of_wave(P, B, EMBED_WAVES, wv, b)) return;
-    // the brick's owner, window count and staged count read together, then the replica
-    // descriptor and the first window entry before the tests (valid memory either way), so
-    // that the chain of dependent reads stays short
-    const int r = B.brick_rep[b];
-    const int nw = B.wcnt[b];
-    const int tot = B.stotal[b];
-    if (r < 0) return;
-    const RepDev &R = B.reps[r];
-    const int lb = b - R.b_off;
+    constexpr int EP = CHUNK / LPP;
     const int64_t S_ = P.nslots;
-    const int64_t base = R.p_off + (int64_t)lb * R.bcap;
-    const int g = lane / CHUNK, ng = VBC_WAVE / CHUNK;
-    const int t_first = B.wlst[base + g];
-    if (nw == 0 || tot > P.stage_cap) return;  // nothing in a window, or an overflowed brick
-    PairR<Real> *pt = ptab[wv];
-    if (MULTI) {
-        const int nt = R.ntypes;
-        if (lane < nt * nt) {
-            const int a = lane / nt, c = lane % nt;
-            pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    // eight lanes per window particle, one entry of each list chunk per lane; neighbours
-    // are gathered from global memory through the brick's staging map
+    const int g = lane / LPP, ng = VBC_WAVE / LPP;
     R2 *sA = (R2 *)B.sA;
     const double *X = B.x[cur];
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
     const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
     const PairR<Real> p0 = pair_r<Real>(R.pair[0], R.rc2);
-    const int e = lane % CHUNK;
+    const int e = lane % LPP;
     for (int k = g; k < nw; k += ng) {
-        int t = k == g ? t_first : B.wlst[base + k];
+        int t = (k == g && t_first >= 0) ? t_first : B.wlst[base + k];
         int64_t i = base + t;
         double n_i = B.nd[i];
         int ti = MULTI ? B.type[i] : 0;
@@ -1309,19 +1287,24 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
             // rows past the list and the padding slot read valid memory and are masked.  The
             // first four rows are read before the list length arrives (rows below nchunk exist
             // for every slot).
-            uint4 qf[4];
+            constexpr int CP = 4 / EP;  // chunks per phase
+            uint4 qf[CP];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) qf[j] = B.nl[(size_t)min(j, P.nchunk - 1) * S_ + i];
-            for (int c0 = 0; c0 < nch; c0 += 4) {
+            for (int j = 0; j < CP; ++j) qf[j] = B.nl[(size_t)min(j, P.nchunk - 1) * S_ + i];
+            for (int c0 = 0; c0 < nch; c0 += CP) {
                 int uj[4], sj[4], wj[4];
                 bool vj[4];
+                uint4 qc[CP];
+#pragma unroll
+                for (int j = 0; j < CP; ++j)
+                    qc[j] = c0 == 0 ? qf[j] : B.nl[(size_t)min(c0 + j, P.nchunk - 1) * S_ + i];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int c = min(c0 + j, P.nchunk - 1);
-                    const uint4 q = c0 == 0 ? qf[j] : B.nl[(size_t)c * S_ + i];
-                    const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
-                    const int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
-                    vj[j] = c0 + j < nch && u != P.stage_cap;
+                    const int jc = j / EP, x = e + LPP * (j % EP);  // chunk, entry
+                    const uint4 q = qc[jc];
+                    const uint32_t wd = (x < 2) ? q.x : (x < 4) ? q.y : (x < 6) ? q.z : q.w;
+                    const int u = (int)((wd >> (16 * (x & 1))) & 0xffffu);
+                    vj[j] = c0 + jc < nch && u != P.stage_cap;
                     uj[j] = vj[j] ? u : 0;
                 }
 #pragma unroll
@@ -1348,10 +1331,11 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
                 }
             }
         } else {
-            for (int c = 0; c < nch; ++c) {
+            for (int cx = 0; cx < nch * EP; ++cx) {
+                const int c = cx / EP, x = e + LPP * (cx % EP);
                 uint4 q = B.nl[(size_t)c * S_ + i];
-                uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
-                int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+                uint32_t wd = (x < 2) ? q.x : (x < 4) ? q.y : (x < 6) ? q.z : q.w;
+                int u = (int)((wd >> (16 * (x & 1))) & 0xffffu);
                 if (R.excl_span > 0) {
                     if (u & 0x8000) continue;  // excluded pair: no attraction between them
                 }
@@ -1373,14 +1357,51 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
                 acc += sdi * (double)(sj * (-q2.E_a * qq * qq));
             }
         }
-        // fixed-order reduction over the eight lanes of the group
+        // fixed-order reduction over the lanes of the group
 #pragma unroll
-        for (int o = CHUNK / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, CHUNK);
+        for (int o = LPP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPP);
         if (e == 0) {
             double A = MULTI ? acc : omega_dd64(n_i, R.pair[0].x1, R.pair[0].x2) * acc;
             sA[i].y = (Real)A;
         }
     }
+}
+
+template <class Real, bool MULTI>
+__global__ void k_embed(Buffers B, Launch P, int cur)
+{
+    __shared__ PairR<Real> ptab[EMBED_WAVES][MAXT * MAXT];
+    const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
+    int b;
+    if (!brick_of_wave(P, B, EMBED_WAVES, wv, b)) return;
+    // the brick's owner, window count and staged count read together, then the replica
+    // descriptor and the first window entry before the tests (valid memory either way), so
+    // that the chain of dependent reads stays short
+    const int r = B.brick_rep[b];
+    const int nw = B.wcnt[b];
+    const int tot = B.stotal[b];
+    if (r < 0) return;
+    const RepDev &R = B.reps[r];
+    const int lb = b - R.b_off;
+    const int64_t S_ = P.nslots;
+    const int64_t base = R.p_off + (int64_t)lb * R.bcap;
+    const int t_first = B.wlst[base + lane / CHUNK];  // for eight lanes per particle
+    if (nw == 0 || tot > P.stage_cap) return;  // nothing in a window, or an overflowed brick
+    PairR<Real> *pt = ptab[wv];
+    if (MULTI) {
+        const int nt = R.ntypes;
+        if (lane < nt * nt) {
+            const int a = lane / nt, c = lane % nt;
+            pt[a * MAXT + c] = pair_r<Real>(R.pair[a * MAXT + c], R.rc2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // eight lanes per particle when a wave takes all of the brick's window particles at once;
+    // with more of them, four lanes each, so that twice as many are in flight
+    if (nw <= VBC_WAVE / CHUNK) embed_brick<CHUNK, Real, MULTI>(B, P, R, pt, b, base, nw, lane, t_first, cur);
+    else embed_brick<4, Real, MULTI>(B, P, R, pt, b, base, nw, lane, -1, cur);
 }
 
 // ---------------------------------------------------------------------------
