@@ -345,7 +345,7 @@ __device__ __forceinline__ void stage_map(const Buffers &B, int b, int stage_cap
 //
 // The map entries of the first four (threadIdx.x + j blockDim.x) are read by map_prefetch
 // as soon as the brick is known, before its header: their latency then overlaps the
-// header's, and the gathers can go out right after the header's barrier.  Entries past the
+// header's, and the gathers can go out as soon as the header is known.  Entries past the
 // staged count are stale but valid slot indices (the map is cleared at creation and only
 // ever holds slots), and their stores are not made.
 struct MapFirst {
