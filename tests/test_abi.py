@@ -76,3 +76,13 @@ def test_option_validation():
 def test_chain_length_must_divide_n():
     with pytest.raises(vbc.VBCError):
         vbc.workspace_size([vbc.replica(101, 20.0, W.vbc_params(), chain_len=10, k_bond=100.0)])
+
+
+def test_empty_inputs_rejected():
+    # a replica without particles, and a call without replicas, are argument errors
+    with pytest.raises(vbc.VBCError) as ei:
+        vbc.workspace_size([vbc.replica(0, 20.0, W.vbc_params())])
+    assert ei.value.status == vbc.VBC_ERR_ARG
+    with pytest.raises(vbc.VBCError) as ei:
+        vbc.workspace_size([])
+    assert ei.value.status == vbc.VBC_ERR_ARG
