@@ -198,3 +198,31 @@ def test_sampled_parity_at_full_size(N, rho, f, nsample):
     assert np.abs(e[idx] - ref["e"]).max() <= 1e-5 * max(1.0, np.abs(e).max())
     assert abs(UW[0, 0].item() - e.sum()) <= 1e-9 * np.abs(e).sum()
     assert np.abs(F.sum(axis=0)).max() <= 1e-5 * np.linalg.norm(F, axis=1).max() * np.sqrt(N)
+
+
+def test_sampled_melt_parity_at_full_size():
+    """The full bead-spring melt (20,000 chains x 50 beads = 10^6 beads at density 0.85,
+    stickers every fifth bead) at its random-walk start, in the launch configuration the
+    benchmark starts it in (FP32 pair arithmetic, bricks of 3^3 cells, k_max 256, sized for
+    local densities up to 2): counts and forces (pair plus bond terms) of sampled beads
+    against the oracle's local evaluation, and the net force."""
+    vbc = _vbc()
+    print("[sampled melt] N=1000000", flush=True)
+    wl = W.polymer_melt(seed=4)
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, mask=wl.mask, chain_len=50,
+                               k_bond=wl.k_bond, r0_bond=wl.r0, skin=W.SKIN),
+                   precision="fp32", brick=3, k_max=256, rho_max=2.0)
+    s.set_state(wl.x, types=wl.types)
+    n = s.count().cpu().numpy()
+    F, e, UW = s.force()
+    s.check()
+    F = F.cpu().numpy()
+    idx = np.random.default_rng(11).choice(wl.N, size=24, replace=False)
+    ref = oracle.evaluate_subset(wl.x, wl.L, wl.params, idx, wl.types, wl.mask)
+    _, Fb = oracle.bonds_energy_forces(wl.x, wl.L, wl.bonds, wl.k_bond, wl.r0)
+    Fref = ref["F"] + Fb[idx]
+    assert np.abs(n[idx] - ref["n"]).max() <= 1e-5
+    err = np.linalg.norm(F[idx] - Fref, axis=1).max() / np.linalg.norm(F, axis=1).max()
+    print(f"  sampled normwise force error {err:.2e}", flush=True)
+    assert err <= 1e-5
+    assert np.abs(F.sum(axis=0)).max() <= 1e-5 * np.linalg.norm(F, axis=1).max() * np.sqrt(wl.N)
