@@ -174,13 +174,14 @@ def test_polymer_melt_parity():
         assert abs(UW[0, 0].item() - (ref["U"] + Ub)) <= tol * (np.abs(ref["e"]).sum() + Ub)
 
 
-@pytest.mark.parametrize("N,rho,f,nsample", [(100_000, 0.3, 3.0, 48), (1_000_000, 0.5, 4.0, 24)])
+@pytest.mark.parametrize("N,rho,f,nsample",
+                         [(100_000, 0.3, float(f), 48) for f in range(1, 7)] + [(1_000_000, 0.5, 4.0, 24)])
 def test_sampled_parity_at_full_size(N, rho, f, nsample):
     """Full-size systems in the benchmark's launch configuration (FP32 pair arithmetic):
     forces and counts of sampled particles against the oracle's local evaluation, plus
     size-independent properties (net force, energy = sum of per-particle energies)."""
     vbc = _vbc()
-    print(f"[sampled] N={N}", flush=True)
+    print(f"[sampled] N={N} f={f}", flush=True)
     wl = W.fluid(N, rho, f, E_a=5.0, seed=17)
     s = vbc.System(vbc.replica(N, wl.L, wl.params), precision="fp32")
     s.set_state(wl.x)
