@@ -333,8 +333,10 @@ vbc_status vbc_pool_create(const vbc_pool_caps *caps, const vbc_options *opt, vo
 /* Admit a replica with its initial state (as vbc_set_state with rep = the new index;
  * arrays of this replica only, stride N) and return its index in *rep.  Stream-ordered
  * after earlier work on s; the other replicas are not touched.  VBC_ERR_CAPACITY if no
- * slot or no contiguous range of slots, bricks, cells or particle indices is free, or if
- * the replica needs a larger brick capacity, k_max or stage_cap than the pool has. */
+ * slot or no contiguous range of slots, bricks, cells or particle indices is free, if
+ * the replica needs a larger brick capacity, k_max or stage_cap than the pool has, or if
+ * its count mask leaves out a type it has and the pool was made with max_types = 1 and
+ * no chains (such a pool runs the one-type kernels, which count every neighbour). */
 vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x,
                      const double *d_v, const int32_t *d_type, uint64_t step0, hipStream_t s,
                      int32_t *rep);

@@ -72,7 +72,7 @@ def lib():
         L.vbco_eval_subset.argtypes = [C.c_int64, dp, i32p, dp, C.c_int, pp, u32p, i64p,
                                        C.c_int64, dp, dp, dp]
         L.vbco_bonds.restype = C.c_double
-        L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp]
+        L.vbco_bonds.argtypes = [C.c_int64, dp, dp, i64p, C.c_int64, C.c_double, C.c_double, dp, dp]
         L.vbco_set_exclusions.restype = None
         L.vbco_set_exclusions.argtypes = [C.c_int64, C.c_int64]
         L.vbco_observables.restype = None
@@ -235,14 +235,20 @@ def evaluate_subset(x, L, params, idx, types=None, mask=None, chain_len=0, excl_
     return {"n": n, "F": F, "e": e}
 
 
-def bonds_energy_forces(x, L, bonds, k, r0):
+def bonds_energy_forces(x, L, bonds, k, r0, virial=False):
+    """Energy and forces (N x 3) of harmonic bonds k/2 (r - r0)^2; with virial=True also
+    the bonds' virial {W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz} (same convention as the
+    pair virial of evaluate)."""
     x = _f64(x)
     N = x.shape[0]
     Lv = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)).copy())
     b = np.ascontiguousarray(bonds, dtype=np.int64).reshape(-1, 2)
     F = np.zeros((N, 3))
+    Wb = np.zeros(7)
     U = lib().vbco_bonds(N, _dp(x), _dp(Lv), b.ctypes.data_as(C.POINTER(C.c_int64)),
-                         b.shape[0], float(k), float(r0), _dp(F))
+                         b.shape[0], float(k), float(r0), _dp(F), _dp(Wb))
+    if virial:
+        return U, F, Wb
     return U, F
 
 

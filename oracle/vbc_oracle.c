@@ -471,12 +471,16 @@ void vbco_eval_subset(int64_t N, const double *x, const int32_t *type, const dou
 /* ------------------------------------------------------------------------- */
 
 /* U_bond = sum over bonds of k/2 (r - r0)^2, minimum image; bonds given as index
- * pairs.  Adds the forces into F (N x 3) and returns the bond energy. */
+ * pairs.  Adds the forces into F (N x 3, or NULL) and returns the bond energy.  W (7
+ * doubles, or NULL) receives the bonds' virial in the convention of the pair terms,
+ * W = -sum_b dU_b/dr r and W_ab = -sum_b dU_b/dr d_a d_b / r, with dU_b/dr = k (r - r0),
+ * ordered {W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz}. */
 double vbco_bonds(int64_t N, const double *x, const double *L, const int64_t *bonds,
-                  int64_t nb, double k, double r0, double *F)
+                  int64_t nb, double k, double r0, double *F, double *W)
 {
     (void)N;
     double U = 0.0;
+    double w[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t b = 0; b < nb; ++b) {
         int64_t i = bonds[2 * b], j = bonds[2 * b + 1];
         double d[3];
@@ -484,14 +488,23 @@ double vbco_bonds(int64_t N, const double *x, const double *L, const int64_t *bo
         double r = sqrt(norm2(d));
         double dr = r - r0;
         U += 0.5 * k * dr * dr;
+        double c = r > 0.0 ? k * dr / r : 0.0; /* dU_b/dr / r */
         if (F && r > 0.0) {
-            double c = k * dr / r;
             for (int a = 0; a < 3; ++a) {
                 F[3 * i + a] -= c * d[a];
                 F[3 * j + a] += c * d[a];
             }
         }
+        w[0] -= c * (r * r);
+        w[1] -= c * d[0] * d[0];
+        w[2] -= c * d[1] * d[1];
+        w[3] -= c * d[2] * d[2];
+        w[4] -= c * d[0] * d[1];
+        w[5] -= c * d[0] * d[2];
+        w[6] -= c * d[1] * d[2];
     }
+    if (W)
+        for (int a = 0; a < 7; ++a) W[a] = w[a];
     return U;
 }
 
@@ -639,7 +652,7 @@ static void total_force(const vbco_sys *s, const int64_t *bonds, int64_t nb, dou
     double UW[8];
     vbco_eval(s->N, s->x, s->type, s->L, s->ntypes, s->P, s->mask, NULL, NULL, F, NULL, UW);
     double Ub = 0.0;
-    if (bonds && nb > 0) Ub = vbco_bonds(s->N, s->x, s->L, bonds, nb, kb, r0, F);
+    if (bonds && nb > 0) Ub = vbco_bonds(s->N, s->x, s->L, bonds, nb, kb, r0, F, NULL);
     if (U) *U = UW[0] + Ub;
 }
 

@@ -68,7 +68,7 @@ struct RepPlan {
 
 // Fixed capacity of a workspace.
 struct Caps {
-    int32_t nrep = 0, ntypes_max = 1, any_chains = 0, any_excl = 0, bcap_max = 0, nh_max = 1, ncb_max = 1;
+    int32_t nrep = 0, ntypes_max = 1, any_chains = 0, any_excl = 0, any_mask = 0, bcap_max = 0, nh_max = 1, ncb_max = 1;
     int64_t ntot = 0, nslots = 0;
     int32_t nbrick = 0, ncell = 0;
 };
@@ -346,6 +346,16 @@ vbc_status plan_replica(const vbc_replica_desc &d, int brick_target, double rho_
     return VBC_OK;
 }
 
+// A count mask that leaves out a type present in the replica: only the general pair path
+// applies masks, so such a replica needs it even with a single type.
+bool partial_mask(const RepDev &R)
+{
+    const uint32_t all = (1u << R.ntypes) - 1u;
+    for (int a = 0; a < R.ntypes; ++a)
+        if ((R.mask[a] & all) != all) return true;
+    return false;
+}
+
 // Workspace layout for a capacity; every array is 256-byte aligned.
 Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
 {
@@ -438,7 +448,7 @@ Launch launch_for(const Caps &C, const vbc_options &opt)
     P.ncb_max = C.ncb_max;
     P.ntypes_max = C.ntypes_max;
     P.any_chains = C.any_chains;
-    P.multi = (C.ntypes_max > 1 || C.any_excl) ? 1 : 0;
+    P.multi = (C.ntypes_max > 1 || C.any_excl || C.any_mask) ? 1 : 0;
     P.precision = opt.precision;
     return P;
 }
@@ -837,6 +847,7 @@ static vbc_status plan_set(const vbc_replica_desc *reps, int32_t nrep, const vbc
         C.ntypes_max = std::max(C.ntypes_max, (int)p.R.ntypes);
         if (p.R.chain_len) C.any_chains = 1;
         if (p.R.excl_span) C.any_excl = 1;
+        if (partial_mask(p.R)) C.any_mask = 1;
         rho_cell_max = std::max(rho_cell_max, p.rho_cell);
         own_mean_max = std::max(own_mean_max, p.own_mean);
         k_mean_max = std::max(k_mean_max, p.k_mean);
@@ -1002,6 +1013,9 @@ vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x,
     const RepDev &R = rp.R;
     if (R.ntypes > h->P.ntypes_max) return hfail(h, VBC_ERR_CAPACITY, "more particle types than the pool allows");
     if (R.chain_len && !h->P.any_chains) return hfail(h, VBC_ERR_CAPACITY, "the pool was made without chains");
+    if (partial_mask(R) && !h->P.multi)
+        return hfail(h, VBC_ERR_CAPACITY,
+                     "a count mask that leaves out a type needs a pool made with max_types > 1 or chains");
     if (R.bcap > h->P.bcap_max)
         return hfail(h, VBC_ERR_CAPACITY, "replica needs " + std::to_string(R.bcap) +
                                               " slots per brick; the pool has " + std::to_string(h->P.bcap_max));

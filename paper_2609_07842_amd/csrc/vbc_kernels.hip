@@ -1,7 +1,7 @@
 // vbc_kernels.hip -- gfx950 kernels of the VBC hot path.
 //
-// Passes (Section 2, "two passes over the neighbour list"; the force itself follows from
-// differentiating eq. (Vhat)):
+// Passes (Section 2, paragraph on the cost of the correction: a count sweep and a force
+// sweep of the neighbour list; the force itself follows from differentiating eq. (Vhat)):
 //   count  : n_i = sum_j omega(r_ij, r_l, r_h)                       eq. (counter)
 //            s_i = omega(n_i, f - delta, f - delta + 1)              eq. (Psi), (Psidelta)
 //   embed  : A_i = dU/dn_i = s'_i sum_j s_j V_a(r_ij), only for particles whose count lies

@@ -147,6 +147,46 @@ def test_multitype_parity_both_precisions():
         assert _normwise(F, ref["F"]) <= tol
 
 
+def test_single_type_count_mask_is_honoured():
+    """One particle type whose count mask leaves out its own type (reading R15: a particle
+    counts only neighbours whose type is in its mask): every count is 0, the switching
+    factors stay 1 and the potential is the plain pair sum.  Both precisions, against the
+    oracle, and different from the all-counting result."""
+    N = 1500
+    L = W.box_length(N, 0.4)
+    x = W.uniform_positions(N, L, seed=41)
+    p = W.vbc_params(E_a=5.0, f=1.0)
+    ref = oracle.evaluate(x, L, p, None, np.array([0], dtype=np.uint32))
+    full = oracle.evaluate(x, L, p)
+    assert np.all(ref["n"] == 0.0) and _normwise(full["F"], ref["F"]) > 1e-2
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        print(f"[mask0] {prec}", flush=True)
+        n, F, e, UW = _gpu_eval(_system(N, L, p, precision=prec, mask=[0]), x)
+        assert np.all(n == 0.0)
+        assert _normwise(F, ref["F"]) <= tol
+        assert abs(UW[0, 0] - ref["U"]) <= tol * max(1.0, np.abs(ref["e"]).sum())
+
+
+def test_single_type_pool_rejects_partial_mask():
+    """A pool made for one type without chains runs the one-type kernels, which count every
+    neighbour: admitting a replica whose mask leaves its type out is refused."""
+    vbc = _vbc()
+    N = 800
+    L = W.box_length(N, 0.3)
+    p = W.vbc_params(E_a=5.0, f=2.0)
+    d = vbc.replica(N, L, p, mask=[0])
+    fp = vbc.footprint(d, "fp32", k_max=72, stage_cap=2112)
+    caps = dict(max_replicas=2, max_types=1, max_particles=2 * N, max_slots=2 * fp["slots"],
+                max_bricks=2 * fp["bricks"], max_cells=2 * fp["cells"], max_bcap=fp["bcap"],
+                chains=False)
+    pool = vbc.Pool(caps, precision="fp32", k_max=72, stage_cap=2112, block=256)
+    with pytest.raises(vbc.VBCError) as ei:
+        pool.admit(d, W.uniform_positions(N, L, 3))
+    assert ei.value.status == vbc.VBC_ERR_CAPACITY
+    pool.admit(vbc.replica(N, L, p), W.uniform_positions(N, L, 3))  # all-counting mask is fine
+    pool.close()
+
+
 def test_single_and_pair_particles():
     p = W.vbc_params(E_a=2.0, f=1.0)
     for N, x in ((1, np.array([[1.0, 2.0, 3.0]])),

@@ -158,8 +158,10 @@ def test_polymer_melt_parity():
     vbc = _vbc()
     wl = W.polymer_melt(nchains=40, nbeads=50, seed=7)
     ref = oracle.evaluate(wl.x, wl.L, wl.params, wl.types, wl.mask)
-    Ub, Fb = oracle.bonds_energy_forces(wl.x, wl.L, wl.bonds, wl.k_bond, wl.r0)
+    Ub, Fb, Wb = oracle.bonds_energy_forces(wl.x, wl.L, wl.bonds, wl.k_bond, wl.r0, virial=True)
     Fref = ref["F"] + Fb
+    # {W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz} of pair terms plus bonds
+    Wref = np.concatenate([[ref["W"]], ref["Wt"]]) + Wb
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
         print(f"[melt] {prec}", flush=True)
         # random-walk starts pack beads at bond distance: size the list for that
@@ -172,6 +174,8 @@ def test_polymer_melt_parity():
         assert np.abs(n - ref["n"]).max() <= (1e-12 if prec == "fp64" else 1e-5)
         assert _normwise(F.cpu().numpy(), Fref) <= tol
         assert abs(UW[0, 0].item() - (ref["U"] + Ub)) <= tol * (np.abs(ref["e"]).sum() + Ub)
+        wscale = np.abs(Wref).max() + np.abs(ref["e"]).sum() + Ub
+        assert np.abs(UW[0, 1:8].cpu().numpy() - Wref).max() <= tol * wscale
 
 
 @pytest.mark.parametrize("N,rho,f,nsample",

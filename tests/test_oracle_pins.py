@@ -118,6 +118,10 @@ def test_worked_examples(case):
         assert close(r["n"], case["n"])
     if "F" in case:
         assert close(r["F"], case["F"]), r["F"]
+    if "W" in case:
+        assert close(r["W"], case["W"]), r["W"]
+    if "Wt" in case:
+        assert close(r["Wt"], case["Wt"]), r["Wt"]
     if "U_without_probe" in case:
         r0 = oracle.evaluate(x[:2], g["box"], g["params"])
         assert close(r0["U"], case["U_without_probe"])
@@ -206,10 +210,50 @@ def test_virial_is_box_scaling_derivative(name, params):
     dU = (up - um) / (2 * h)
     assert abs(r["W"] + dU) < 1e-6 * max(1.0, abs(r["W"]))
     assert abs(r["Wt"][:3].sum() - r["W"]) < 1e-10 * max(1.0, abs(r["W"]))
-    # anisotropic scaling along x only gives W_xx
-    upx = oracle.evaluate(x * np.array([1 + h, 1, 1]), np.array([L * (1 + h), L, L]), params)["U"]
-    umx = oracle.evaluate(x * np.array([1 - h, 1, 1]), np.array([L * (1 - h), L, L]), params)["U"]
-    assert abs(r["Wt"][0] + (upx - umx) / (2 * h)) < 1e-6 * max(1.0, abs(r["W"]))
+    # anisotropic scaling along one axis a gives W_aa (Wt holds xx, yy, zz, xy, xz, yz)
+    for a in range(3):
+        s = np.ones(3)
+        s[a] = 1 + h
+        up_a = oracle.evaluate(x * s, L * s, params)["U"]
+        s[a] = 1 - h
+        um_a = oracle.evaluate(x * s, L * s, params)["U"]
+        assert abs(r["Wt"][a] + (up_a - um_a) / (2 * h)) < 1e-6 * max(1.0, abs(r["W"])), a
+
+
+def _open_cluster(N, seed, L=60.0, size=5.0):
+    """N particles in a cube of edge `size` in the middle of a box of edge L, no pair near
+    closer than 0.3: no pair interacts through a periodic image."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < N:
+        p = rng.uniform(0.5 * (L - size), 0.5 * (L + size), size=3)
+        if all(np.linalg.norm(p - q) > 0.3 for q in pts):
+            pts.append(p)
+    return np.array(pts), L
+
+
+@pytest.mark.parametrize("name,params", PARAM_CASES[:3] + PARAM_CASES[5:], ids=[c[0] for c in PARAM_CASES[:3] + PARAM_CASES[5:]])
+def test_virial_offdiagonal_is_shear_derivative(name, params):
+    # for an open cluster U depends only on the pair distances, so under the shear
+    # x_a -> x_a + eps x_b (a != b) dU/deps = sum_{i<j} (dU/dr) d_a d_b / r = -W_ab
+    x, L = _open_cluster(40, seed=13)
+    r = oracle.evaluate(x, L, params)
+    h = 1e-6
+    for k, (a, b) in enumerate(((0, 1), (0, 2), (1, 2))):
+        xp = x.copy()
+        xp[:, a] += h * x[:, b]
+        xm = x.copy()
+        xm[:, a] -= h * x[:, b]
+        dU = (oracle.evaluate(xp, L, params)["U"] - oracle.evaluate(xm, L, params)["U"]) / (2 * h)
+        assert abs(r["Wt"][3 + k] + dU) < 1e-6 * max(1.0, abs(r["W"])), (a, b)
+    # the same cluster scaled about the origin gives the diagonal and the trace
+    for a in range(3):
+        s = np.ones(3)
+        s[a] = 1 + h
+        up = oracle.evaluate(x * s, L, params)["U"]
+        s[a] = 1 - h
+        um = oracle.evaluate(x * s, L, params)["U"]
+        assert abs(r["Wt"][a] + (up - um) / (2 * h)) < 1e-6 * max(1.0, abs(r["W"])), a
 
 
 # ---------------------------------------------------------------------------
@@ -466,6 +510,40 @@ def test_langevin_equipartition_interacting():
     K = out["K"][2000:]
     T = 2 * K.mean() / (3 * N)
     assert abs(T - 1.0) < 0.06
+
+
+def test_bond_single_bond_closed_form():
+    # U_bond = k/2 (r - r0)^2 with k = 100, r0 = 1 (the melt's bonds): at r = 1.25 and at
+    # r = 0.75 the energy is 50 * 0.0625 = 3.125 and the force magnitude k |r - r0| = 25,
+    # pulling the beads together when stretched and apart when compressed; the virial
+    # W = -(dU/dr) r = -100 * 0.25 * 1.25 = -31.25 (stretched) and +18.75 (compressed),
+    # all along x.  Every value is exact in binary FP64.
+    for r, Uex, Fx, Wex in ((1.25, 3.125, 25.0, -31.25), (0.75, 3.125, -25.0, 18.75)):
+        x = np.array([[10.0, 10.0, 10.0], [10.0 + r, 10.0, 10.0]])
+        U, F, Wb = oracle.bonds_energy_forces(x, 20.0, [[0, 1]], 100.0, 1.0, virial=True)
+        assert U == Uex
+        assert np.array_equal(F, np.array([[Fx, 0.0, 0.0], [-Fx, 0.0, 0.0]]))
+        assert np.array_equal(Wb, np.array([Wex, Wex, 0.0, 0.0, 0.0, 0.0, 0.0]))
+
+
+def test_bond_virial_is_box_scaling_derivative():
+    x, bonds, bead = W.random_walk_chains(3, 6, 20.0, seed=2)
+    x = x + np.random.default_rng(1).normal(scale=0.1, size=x.shape)
+    L = 20.0
+    U, F, Wb = oracle.bonds_energy_forces(x, L, bonds, 100.0, 1.0, virial=True)
+    h = 1e-6
+    for a in range(4):  # 0..2: scale one axis (W_aa); 3: all axes (W)
+        s = np.ones(3)
+        if a < 3:
+            s[a] = 1 + h
+        else:
+            s[:] = 1 + h
+        up = oracle.bonds_energy_forces(x * s, L * s, bonds, 100.0, 1.0)[0]
+        s = 2.0 - s
+        um = oracle.bonds_energy_forces(x * s, L * s, bonds, 100.0, 1.0)[0]
+        ref = Wb[1 + a] if a < 3 else Wb[0]
+        assert abs(ref + (up - um) / (2 * h)) < 1e-6 * max(1.0, abs(Wb[0])), a
+    assert abs(Wb[1:4].sum() - Wb[0]) < 1e-12 * max(1.0, abs(Wb[0]))
 
 
 def test_bond_forces_gradient():
