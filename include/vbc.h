@@ -228,6 +228,20 @@ vbc_status vbc_cluster_scratch_size(vbc_handle h, size_t *bytes);
 vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int32_t *d_label,
                         int64_t *d_stats, int64_t *d_hist, int32_t hist_len, hipStream_t s);
 
+/* vbc_clusters without caller scratch, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * outputs, arguments and errors as vbc_clusters; the scratch is a fixed array of
+ * VBC_CLUSTERS_NOALLOC_BYTES that the library holds in every GPU it runs on until the
+ * process ends (its address is looked up on the first call on a device).  The call
+ * allocates and frees nothing.  Returns VBC_ERR_CAPACITY when the handle needs more
+ * scratch than that (vbc_cluster_scratch_size: 20 bytes per particle slot, about 1.6 x 10^6
+ * slots fit).  All calls on one GPU share the array, which keeps the last call's contents
+ * (each call rewrites what it reads first): calls that overlap in time on one GPU, on
+ * different streams or handles, race and give wrong results, so order them. */
+#define VBC_CLUSTERS_NOALLOC_BYTES (32u << 20)
+vbc_status vbc_clusters_noalloc(vbc_handle h, int32_t *d_label, int64_t *d_stats, int64_t *d_hist,
+                                int32_t hist_len, hipStream_t s);
+
 /* Bond lifetimes (Section 4, "Bond lifetimes"): one sample of a tracker that follows every
  * bond (r_ij < r_a of the pair, the criterion of vbc_observables) from the first sample at
  * which it is seen to the first sample without it, at the replicas' current step counters.

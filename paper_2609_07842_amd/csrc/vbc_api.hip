@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1322,6 +1323,54 @@ vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int
     W.z = (int32_t *)(base + 4 * a);
     VBC_TRY(h, launch_clusters(h->B, h->P, h->cur, W, d_label, d_stats, d_hist, d_hist ? hist_len : 0, s), "clusters");
     return VBC_OK;
+}
+
+// Scratch of vbc_clusters_noalloc: one fixed array in every GPU's memory, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device memory:
+// kernels and copies get the device address from hipGetSymbolAddress, looked up once per
+// device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[VBC_CLUSTERS_NOALLOC_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up on the first call on
+// that device, with the device current).
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+vbc_status vbc_clusters_noalloc(vbc_handle h, int32_t *d_label, int64_t *d_stats, int64_t *d_hist,
+                                int32_t hist_len, hipStream_t s)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    const size_t need = 5 * cluster_array_bytes(h->P);
+    if (need > (size_t)VBC_CLUSTERS_NOALLOC_BYTES)
+        return hfail(h, VBC_ERR_CAPACITY,
+                     "cluster scratch of " + std::to_string(need) + " bytes exceeds the library's fixed " +
+                         std::to_string((size_t)VBC_CLUSTERS_NOALLOC_BYTES) +
+                         " bytes: use vbc_clusters with caller scratch");
+    void *p = nullptr;
+    VBC_TRY(h, scratch_address(&p), "hipGetSymbolAddress(scratch)");
+    // every scratch array is rewritten by the analysis' first kernel before it is read
+    return vbc_clusters(h, p, need, d_label, d_stats, d_hist, hist_len, s);
 }
 
 static size_t track_part(size_t b) { return (b + 255) & ~(size_t)255; }

@@ -31,7 +31,7 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
            "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set",
            "vbc_observables", "vbc_cluster_scratch_size", "vbc_clusters", "vbc_bond_track_size",
-           "vbc_bond_track")
+           "vbc_bond_track", "vbc_clusters_noalloc")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -117,6 +117,7 @@ def lib():
             "vbc_observables": [vp, dp, dp, dp, vp],
             "vbc_cluster_scratch_size": [vp, C.POINTER(C.c_size_t)],
             "vbc_clusters": [vp, dp, C.c_size_t, dp, dp, dp, i32, vp],
+            "vbc_clusters_noalloc": [vp, dp, dp, dp, i32, vp],
             "vbc_bond_track_size": [vp, i32, C.POINTER(C.c_size_t)],
             "vbc_bond_track": [vp, dp, C.c_size_t, i32, i32, dp, i32, i64, dp, vp],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
@@ -345,6 +346,17 @@ class _Handle:
         hist = torch.empty((self.nslot, 2, hist_len), dtype=torch.int64, device=self.device) if hist_len else None
         self._ok(lib().vbc_clusters(self.h, _ptr(scratch), nb.value, _ptr(lab), _ptr(stats), _ptr(hist),
                                     int(hist_len), self._stream()))
+        return lab, stats, hist
+
+    def clusters_noalloc(self, hist_len=0, labels=True):
+        """As clusters(), with the library's own fixed scratch (vbc_clusters_noalloc)
+        instead of a scratch tensor."""
+        torch = self.torch
+        lab = torch.empty(self.stride, dtype=torch.int32, device=self.device) if labels else None
+        stats = torch.empty((self.nslot, 5), dtype=torch.int64, device=self.device)
+        hist = torch.empty((self.nslot, 2, hist_len), dtype=torch.int64, device=self.device) if hist_len else None
+        self._ok(lib().vbc_clusters_noalloc(self.h, _ptr(lab), _ptr(stats), _ptr(hist), int(hist_len),
+                                            self._stream()))
         return lab, stats, hist
 
     def bond_tracker(self, max_partners=16, hist_len=4096, bin_steps=1):
