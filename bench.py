@@ -78,8 +78,18 @@ def measured_traffic(kernel: str):
     return rec["kernels"][kernel]["traffic_bytes"]
 
 
-def cpu_baseline(wl, target_s=15.0):
-    """The FP64 oracle on a bounded sample of the same workload: full VBC forces of m
+def _oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def _pairs_within(x, L, rc):
+    """Ordered pairs closer than rc (the pair evaluations one VBC evaluation delivers)."""
+    from scipy.spatial import cKDTree
+    return 2 * len(cKDTree(x, boxsize=L).query_pairs(rc))
+
+
+def cpu_baseline(wl, target_s=12.0):
+    """The FP64 oracle on a bounded sample of the headline workload: full VBC forces of m
     particles of the N = 10^6 configuration (each needs O(N) scans for its own and its
     neighbours' counts).  Returns pair evaluations delivered per second."""
     import oracle
@@ -88,7 +98,7 @@ def cpu_baseline(wl, target_s=15.0):
     rng = np.random.default_rng(123)
     rc = max(wl.params["r_r"], wl.params["r_a"], wl.params["r_h"])
     tree = cKDTree(wl.x, boxsize=wl.L)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = _oracle_threads()
     # calibrate on one batch of `cores` particles, then size the measured sample
     idx = rng.choice(wl.N, size=cores, replace=False)
     t0 = time.perf_counter()
@@ -104,6 +114,78 @@ def cpu_baseline(wl, target_s=15.0):
             "sample": f"{m} particles of the N={wl.N} start configuration: FP64 forces by the "
                       f"O(N^2) oracle ({pairs} pair evaluations in {dt:.1f} s)",
             "seconds": dt}
+
+
+_SMALL_CASE = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_2609_07842_amd import workloads as W
+wl = W.small_fluid()
+t0 = time.perf_counter(); oracle.evaluate(wl.x, wl.L, wl.params); t1 = time.perf_counter()
+oracle.run(wl.x, wl.v, wl.L, wl.params, 100, kind=oracle.NVE, dt=0.005); t2 = time.perf_counter()
+print(json.dumps({{"eval_s": t1 - t0, "run100_s": t2 - t1}}))
+"""
+
+
+def cpu_cases():
+    """The oracle on the small cases beside the GPU: the N = 1000 NVE configuration in full
+    (one evaluation and 100 velocity-Verlet steps, FP64) on all host threads and on one, and
+    single evaluations of uniform fluids (density 0.3, f = 2) at N = 10^3 and 10^4 in full
+    and at N = 10^5 as a sample of particles, with the full O(N^2) evaluation extrapolated
+    from the N = 10^4 rate (labelled).  Pair visits are the three all-pairs sweeps over
+    N (N - 1) ordered pairs of one evaluation; pair evaluations are the ordered pairs
+    inside the cutoff."""
+    import subprocess
+
+    import oracle
+    from paper_2609_07842_amd import workloads as W
+
+    cores = _oracle_threads()
+    out = {"cores": cores, "kind": "oracle"}
+    wl = W.small_fluid()
+    pe = _pairs_within(wl.x, wl.L, 2.0)
+    t0 = time.perf_counter()
+    oracle.evaluate(wl.x, wl.L, wl.params)
+    t1 = time.perf_counter()
+    oracle.run(wl.x, wl.v, wl.L, wl.params, 100, kind=oracle.NVE, dt=0.005)
+    t2 = time.perf_counter()
+    visits = 3 * wl.N * (wl.N - 1)
+    out["small_fluid_N1000_nve100"] = {
+        "eval_s": t1 - t0, "run100_s": t2 - t1, "steps_per_s": 100 / (t2 - t1),
+        "particle_steps_per_s": 100 * wl.N / (t2 - t1), "pair_visits_per_s": 101 * visits / (t2 - t0),
+        "pair_evals_per_eval": pe}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _SMALL_CASE.format(root=ROOT)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode == 0:
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        one["steps_per_s"] = 100 / one["run100_s"]
+        one["particle_steps_per_s"] = 100 * wl.N / one["run100_s"]
+        out["small_fluid_N1000_nve100_one_core"] = one
+    else:
+        out["small_fluid_N1000_nve100_one_core"] = {"error": r.stderr[-400:]}
+    rate_1e4 = None
+    for N in (1_000, 10_000):
+        f = W.fluid(N, 0.3, 2.0, E_a=5.0, seed=1)
+        t0 = time.perf_counter()
+        oracle.evaluate(f.x, f.L, f.params)
+        dt = time.perf_counter() - t0
+        v = 3 * N * (N - 1)
+        out[f"eval_N{N}"] = {"seconds": dt, "pair_visits_per_s": v / dt,
+                             "pair_evals_per_s": _pairs_within(f.x, f.L, 2.0) / dt}
+        rate_1e4 = v / dt
+    N = 100_000
+    f = W.fluid(N, 0.3, 2.0, E_a=5.0, seed=1)
+    idx = np.random.default_rng(7).choice(N, size=max(cores, 64), replace=False)
+    t0 = time.perf_counter()
+    oracle.evaluate_subset(f.x, f.L, f.params, idx)
+    dt = time.perf_counter() - t0
+    out["eval_N100000"] = {"sample_particles": len(idx), "sample_seconds": dt,
+                           "full_eval_seconds_extrapolated_N2_from_N1e4": 3 * N * (N - 1) / rate_1e4,
+                           "note": "full O(N^2) evaluation not run: time extrapolated as N^2 from the "
+                                   "measured N = 10^4 pair-visit rate"}
+    return out
 
 
 def achievable_copy(torch, nbytes=1 << 30, reps=10):
@@ -149,7 +231,10 @@ def measure_clusters(s, wl, torch, kbar, reps=5):
                       "labels and histograms) on the launch stream"}
 
 
-def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
+RELAX_STEPS = 2000
+
+
+def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0, relax=RELAX_STEPS):
     from paper_2609_07842_amd import tune
     wl = W.headline(f=f, seed=seed)
     # brick edge and workgroup size from the autotuner's cache when it has this workload
@@ -161,13 +246,15 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
     s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32", **layout)
     s.set_state(wl.x, wl.v)
     integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=seed)
-    # warmup: relax the random start and reach a steady rebuild rate
-    done = 0
-    while done < warmup:
-        k = min(500, warmup - done)
-        s.step(k, **integ)
-        done += k
+    # input preparation (untimed): relax the uniform random start, so that the steps timed
+    # run at the fluid's steady list-rebuild rate rather than in its first transient; then
+    # the warm-up steps
+    for n in [500] * (relax // 500) + [relax % 500] + [500] * (warmup // 500) + [warmup % 500]:
+        if n:
+            s.step(n, **integ)
     s.check()
+    # capture the step graphs of the timed call before the timed region
+    s.prepare_step(steps, **integ)
     st0 = s.stats()[0]
     # timed region: K whole steps, launched as captured step graphs
     torch.cuda.synchronize()
@@ -182,11 +269,29 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
     pair_evals = (st1["pair_evals"] - st0["pair_evals"]) / max(evals, 1)
     builds = st1["builds"] - st0["builds"]
     kbar = st1["list_entries"] / wl.N
-    prof, elapsed_prof = None, None
+    thermo = prof = elapsed_prof = builds_prof = None
     if profile:
-        # second timed region of K steps continuing the same trajectory, every kernel
-        # launched individually between HIP events on the launch stream
+        # K more steps with the energy and the virial of every step accumulated (pass 2 in
+        # full: forces, energy, virial), timed the same way
+        s.thermo(True)
+        s.prepare_step(steps, **integ)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.step(steps, **integ)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t2
+        th = s.thermo_read()[0]
+        s.thermo(False)
+        s.check()
+        thermo = {"timesteps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+                  "steps_accumulated": th["steps"], "mean_U_per_particle": th["sum"][0] / max(th["steps"], 1) / wl.N,
+                  "mean_W_per_particle": th["sum"][1] / max(th["steps"], 1) / wl.N,
+                  "what": "every step also sums the pair energies and the virial (scalar and "
+                          "tensor) per brick in FP64 and reduces them per replica"}
+        # a third region of K steps continuing the same trajectory, every kernel launched
+        # individually between HIP events on the launch stream
         s.profile(True, max_launches=steps + 8)
+        st2 = s.stats()[0]
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         s.step(steps, **integ)
@@ -195,12 +300,43 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0):
         prof = s.profile_read()
         s.profile(False)
         s.check()
+        builds_prof = s.stats()[0]["builds"] - st2["builds"]
     clusters = measure_clusters(s, wl, torch, kbar) if profile else None
     out = dict(wl=wl, elapsed=elapsed, pair_evals_per_step=pair_evals, builds=builds, kbar=kbar,
-               prof=prof, elapsed_prof=elapsed_prof, opts=s.options(), clusters=clusters)
+               prof=prof, elapsed_prof=elapsed_prof, builds_prof=builds_prof, thermo=thermo,
+               opts=s.options(), clusters=clusters, relax=relax)
     s.close()
     del s
     torch.cuda.empty_cache()
+    return out
+
+
+def kernel_table(main_run, N, steps):
+    """Per kernel class: time per launch and per step from the event-timed region, and its
+    algorithmic bytes over that time as a fraction of HBM peak.  The list-build class
+    launches on every step but builds only when a particle has moved more than half the
+    buffer, so its bytes are those of one build and its time is the class total over the
+    builds that happened (empty launches included)."""
+    prof, kbar = main_run["prof"], main_run["kbar"]
+    out = {}
+    for k in ("build", "count", "embed", "force", "kick", "reduce"):
+        ms, n = prof[k]
+        e = {"launches": n, "total_ms": ms, "per_step_us": 1e3 * ms / steps,
+             "mean_launch_us": 1e3 * ms / n if n else None}
+        nb = kernel_bytes(k, N, kbar, "fp32")
+        if k == "build":
+            nbld = main_run["builds_prof"] or 0
+            e["builds"] = nbld
+            e["us_per_build"] = 1e3 * ms / nbld if nbld else None
+            t_unit = ms / nbld * 1e-3 if nbld else None
+        else:
+            t_unit = ms / n * 1e-3 if n else None
+        if t_unit and nb == nb:
+            e["bytes_per_unit"] = nb
+            e["achieved_GBs"] = nb / t_unit / 1e9
+            e["frac"] = e["achieved_GBs"] / HBM_PEAK_GBS
+            e["traffic"] = measured_traffic(k)
+        out[k] = e
     return out
 
 
@@ -276,6 +412,45 @@ def run_paper_table(W, vbc, torch, steps=20000, warmup=2000, seed=8):
     return out
 
 
+def gpu_cases(W, vbc, torch):
+    """The GPU on the oracle's small cases: the N = 1000 NVE configuration in full (FP64:
+    one force evaluation, then 100 velocity-Verlet steps) and single force evaluations of
+    uniform fluids (density 0.3, f = 2) at N = 10^3, 10^4 and 10^5 in both precisions (mean
+    of 20 evaluations after one warm call, energies and virial included)."""
+    out = {}
+    wl = W.small_fluid()
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params), precision="fp64")
+    s.set_state(wl.x, wl.v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.force()
+    s.step(100, integrator="nve", dt=0.005)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.check()
+    s.close()
+    out["small_fluid_N1000_nve100"] = {"seconds": dt, "steps_per_s": 100 / dt,
+                                       "note": "wall time of the first evaluation (list build "
+                                               "included) and 100 steps (graph capture included)"}
+    for N in (1_000, 10_000, 100_000):
+        f = W.fluid(N, 0.3, 2.0, E_a=5.0, seed=1)
+        for prec in ("fp64", "fp32"):
+            s = vbc.System(vbc.replica(N, f.L, f.params), precision=prec)
+            s.set_state(f.x)
+            s.force()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(20):
+                s.force()
+            ev1.record()
+            torch.cuda.synchronize()
+            s.check()
+            out[f"eval_N{N}_{prec}"] = {"ms_per_eval": ev0.elapsed_time(ev1) / 20}
+            s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,9 +460,12 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the small GPU cases beside the oracle's")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-melt", action="store_true")
     ap.add_argument("--no-paper-table", action="store_true")
+    ap.add_argument("--relax", type=int, default=RELAX_STEPS,
+                    help="untimed Langevin steps that relax the random start before the warm-up")
     ap.add_argument("--rho-max", type=float, default=0.0,
                     help="size the main run's layout for local densities up to this value")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -311,27 +489,27 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
 
-    main_run = run_one(W, vbc, torch, args.f, args.steps, args.warmup, args.seed, rho_max=args.rho_max)
+    main_run = run_one(W, vbc, torch, args.f, args.steps, args.warmup, args.seed, rho_max=args.rho_max,
+                       relax=args.relax)
     wl = main_run["wl"]
     K = args.steps
     tsps = K / main_run["elapsed"]
     pe_step = main_run["pair_evals_per_step"]
-    prof = main_run["prof"]
-    kernels = {k: {"mean_us": 1e3 * ms / n if n else None, "launches": n, "total_ms": ms}
-               for k, (ms, n) in prof.items()}
-    dom = max(("build", "count", "embed", "force"), key=lambda k: prof[k][0])
-    ms, n = prof[dom]
-    mean_s = ms / n / 1e3
-    nbytes = kernel_bytes(dom, wl.N, main_run["kbar"], "fp32")
-    achieved = nbytes / mean_s / 1e9
+    kernels = kernel_table(main_run, wl.N, K)
+    # the dominant kernel: the largest share of the step time
+    dom = max(("build", "count", "embed", "force"), key=lambda k: kernels[k]["per_step_us"])
+    kd = kernels[dom]
     copy_gbs = achievable_copy(torch)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "achievable_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                "traffic": measured_traffic(dom),
-                "bytes_per_launch": nbytes, "mean_launch_us": mean_s * 1e6,
-                "timing": "HIP events around every launch in a second timed region of the same "
-                          "K steps (individual launches instead of step graphs)",
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kd.get("achieved_GBs"), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": kd.get("frac"), "traffic": kd.get("traffic"),
+                "bytes_per_launch": kd.get("bytes_per_unit"),
+                "mean_launch_us": kd["us_per_build"] if dom == "build" else kd["mean_launch_us"],
+                "achievable_copy_GBs": copy_gbs,
+                "frac_of_copy": kd["achieved_GBs"] / copy_gbs if kd.get("achieved_GBs") else None,
+                "per_kernel_frac": {k: v.get("frac") for k, v in kernels.items() if v.get("frac")},
+                "timing": "HIP events on the launch stream around every launch of each kernel class "
+                          "in a third region of K steps (individual launches instead of step graphs); "
+                          "the list build's bytes are one build's, over its time per build",
                 "ms_per_step_event_region": 1e3 * main_run["elapsed_prof"] / K}
     # whole-step view: all kernels' algorithmic bytes per step over the step time
     step_bytes = (kernel_bytes("count", wl.N, main_run["kbar"], "fp32")
@@ -383,7 +561,12 @@ def main():
                    "throughput_batched_over_one_at_a_time": res["speedup_throughput"],
                    **res}
 
-    cpu = None if args.no_cpu else cpu_baseline(wl)
+    gpu_small = None if args.no_small else gpu_cases(W, vbc, torch)
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] oracle on the host", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl)
+        cpu["cases"] = cpu_cases()
 
     line = {
         "metric": METRIC,
@@ -398,12 +581,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 pair arithmetic, f64 counts/switching/integration/reductions",
         "data": "synthetic",
-        "config": {"workload": "N=1,000,000 uniform-random start, density 0.5, valency 4, "
-                               "eps=5kT, standard VBC(1.5,2.0,0), skin 0.4, Langevin kT=1 "
-                               "gamma=0.1 dt=0.005",
+        "config": {"workload": "N=1,000,000 fluid at density 0.5, valency 4, eps=5kT, standard "
+                               "VBC(1.5,2.0,0), skin 0.4, Langevin kT=1 gamma=0.1 dt=0.005; "
+                               f"uniform-random start relaxed by {main_run['relax']} untimed steps "
+                               "before the warm-up",
                    "N": wl.N, "rho": 0.5, "f": args.f, "E_a": 5.0, "precision": "fp32_mixed",
                    "parallelism": "single GPU"},
         "timesteps_per_s": tsps,
+        "timesteps_per_s_with_energy_virial": (main_run["thermo"] or {}).get("timesteps_per_s"),
+        "energy_virial_run": main_run["thermo"],
         "particle_steps_per_s": tsps * wl.N,
         "pair_evals_per_step": pe_step,
         "list_entries_per_particle": main_run["kbar"],
@@ -417,6 +603,7 @@ def main():
         "paper_table_config": paper_table,
         "polymer_melt": melt,
         "serving": serving,
+        "gpu_small_cases": gpu_small,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -183,6 +183,25 @@ vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipSt
  * calls replay graphs of 8 steps. */
 vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s);
 
+/* Capture, without launching anything, the step graphs that vbc_step(h, nsteps, it, ...)
+ * issued next would launch (the whole-call graph for nsteps <= 64, else the 8-step graph),
+ * so that a later call does not pay for the capture.  No state is read or changed.
+ * Returns VBC_OK also when graphs are off (kernel timing on). */
+vbc_status vbc_step_prepare(vbc_handle h, int32_t nsteps, const vbc_integrator *it);
+
+/* Energy and virial of every step (Section 2, two-passes paragraph: the force pass also
+ * gives the energy of eq. (Vhat) and the virial).  enable != 0: from now on the force pass of
+ * every step of vbc_step also sums, per brick in FP64, the pair energies (plus bond
+ * energies) and the virial {W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz} of the step's new
+ * positions (conventions of vbc_force), and reduces them per replica in a fixed order into
+ * accumulators in the workspace; enable = 0 stops it.  Either way the accumulators are
+ * cleared (on stream s).  vbc_thermo_read synchronises s and returns per replica slot
+ * (host array [slots][17]): the number of steps accumulated, the last step's 8 values
+ * {U, W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz} and the sums of the 8 over those steps; then
+ * it clears the accumulators.  Free slots read 0. */
+vbc_status vbc_thermo(vbc_handle h, int32_t enable, hipStream_t s);
+vbc_status vbc_thermo_read(vbc_handle h, hipStream_t s, double *out);
+
 /* Synchronise s and report the flag word of each replica slot (host array [nrep] or
  * [max_replicas], may be NULL; 0 for free slots);
  * returns the first error among them (overflow or non-finite) and clears the error bits. */

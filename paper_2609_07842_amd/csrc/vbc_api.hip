@@ -13,50 +13,12 @@
 #include <string>
 #include <vector>
 
+#include "arena.h"
 #include "vbc_internal.h"
 
 using namespace vbc;
 
 namespace {
-
-// First-fit allocator of contiguous index ranges [0, cap).
-struct Arena {
-    std::map<int64_t, int64_t> free;  // start -> length
-    void init(int64_t cap)
-    {
-        free.clear();
-        if (cap > 0) free[0] = cap;
-    }
-    int64_t take(int64_t n)
-    {
-        if (n <= 0) return 0;
-        for (auto it = free.begin(); it != free.end(); ++it) {
-            if (it->second < n) continue;
-            int64_t start = it->first, len = it->second;
-            free.erase(it);
-            if (len > n) free[start + n] = len - n;
-            return start;
-        }
-        return -1;
-    }
-    void give(int64_t start, int64_t n)
-    {
-        if (n <= 0) return;
-        auto it = free.emplace(start, n).first;
-        auto nx = std::next(it);
-        if (nx != free.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free.erase(nx);
-        }
-        if (it != free.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free.erase(it);
-            }
-        }
-    }
-};
 
 // Per-replica geometry and the automatic choices it implies.
 struct RepPlan {
@@ -78,7 +40,7 @@ struct Offsets {
     size_t reps, brick_rep, wl0, wl1, wl_n, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
         bfill, x0, x1, v, Fst, xref, tag, type, lcell, xs, vs, tags, types, lcells, src, inv,
         smap, wmap, stotal, nl, nn, nd, sA, wcnt, wlst, part, flags, step, stats, bevals, bentries,
-        stamps, stamp_n;
+        stamps, stamp_n, thermo;
     size_t bytes;
 };
 
@@ -104,10 +66,12 @@ struct vbc_handle_s {
     int prof_n[VBC_NK] = {0, 0, 0, 0, 0, 0};
     // step time stamps (vbc_stamps)
     bool stamps = false;
+    // energy and virial of every step accumulated per replica (vbc_thermo)
+    bool thermo = false;
     // captured step graphs
     struct GraphEntry {
         int kind, nsteps, c;
-        bool stamps;
+        bool stamps, thermo;
         StepArgs st;
         hipGraphExec_t exec;
     };
@@ -410,6 +374,7 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
     o.bentries = carve(off, sizeof(uint32_t) * nb);
     o.stamps = carve(off, sizeof(unsigned long long) * STAMP_CAP);
     o.stamp_n = carve(off, sizeof(unsigned long long));
+    o.thermo = carve(off, sizeof(double) * THERMO_WORDS * nr);
     o.bytes = off;
     return o;
 }
@@ -422,7 +387,8 @@ size_t footprint_bytes(const RepPlan &rp, int precision, int nchunk, int stage_c
     size_t per_brick = 4 * 8 + 5 * (size_t)stage_cap + 4 + 64 + 8 + 4;
     size_t per_cell = 5 * 4;
     return per_slot * (size_t)rp.slots + per_brick * (size_t)rp.R.nbrick +
-           per_cell * (size_t)rp.R.ncell + 4 * (size_t)rp.R.n + sizeof(RepDev) + 4 + 8 + 32;
+           per_cell * (size_t)rp.R.ncell + 4 * (size_t)rp.R.n + sizeof(RepDev) + 4 + 8 + 32 +
+           8 * THERMO_WORDS;
 }
 
 // Launch shape and LDS bounds for a capacity.
@@ -580,6 +546,7 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     B.bentries = at<uint32_t>(d_ws, o.bentries);
     B.stamps = at<unsigned long long>(d_ws, o.stamps);
     B.stamp_n = at<unsigned long long>(d_ws, o.stamp_n);
+    B.thermo = at<double>(d_ws, o.thermo);
 
     hipError_t e = hipHostMalloc((void **)&h->up, sizeof(RepDev) * std::max(C.nrep, 1), hipHostMallocDefault);
     if (e == hipSuccess) {
@@ -747,8 +714,10 @@ static hipError_t launch_step(vbc_handle h, int c, const StepArgs &st, Mode mode
     if (e == hipSuccess) e = timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, c, s); });
     if (e == hipSuccess)
         e = timed(h, VBC_K_FORCE, s, [&] {
-            return launch_force(h->B, h->P, c, mode, false, st, nullptr, nullptr, s);
+            return launch_force(h->B, h->P, c, mode, h->thermo, st, nullptr, nullptr, s);
         });
+    if (e == hipSuccess && h->thermo)
+        e = timed(h, VBC_K_REDUCE, s, [&] { return launch_thermo_acc(h->B, h->P, s); });
     if (e == hipSuccess && h->stamps) e = launch_stamp(h->B, s);
     return e;
 }
@@ -774,7 +743,7 @@ static hipError_t get_graph(vbc_handle h, int kind, int nsteps, int c, const Ste
 {
     for (auto &g : h->graphs)
         if (g.kind == kind && g.nsteps == nsteps && g.c == c && g.stamps == h->stamps &&
-            same_step_args(g.st, st)) {
+            g.thermo == h->thermo && same_step_args(g.st, st)) {
             *out = g.exec;
             return hipSuccess;
         }
@@ -810,7 +779,7 @@ static hipError_t get_graph(vbc_handle h, int kind, int nsteps, int c, const Ste
         (void)hipGraphExecDestroy(h->graphs.front().exec);
         h->graphs.erase(h->graphs.begin());
     }
-    h->graphs.push_back({kind, nsteps, c, h->stamps, st, ex});
+    h->graphs.push_back({kind, nsteps, c, h->stamps, h->thermo, st, ex});
     *out = ex;
     return hipSuccess;
 }
@@ -1183,17 +1152,18 @@ vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipSt
     return VBC_OK;
 }
 
-vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s)
+static vbc_status check_integrator(vbc_handle h, int32_t nsteps, const vbc_integrator *it)
 {
-    if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
-    VBC_NEED_STATE(h);
     if (nsteps < 0) return hfail(h, VBC_ERR_ARG, "nsteps must be >= 0");
     if (it->kind != VBC_NVE && it->kind != VBC_LANGEVIN) return hfail(h, VBC_ERR_ARG, "bad integrator kind");
     if (!(it->dt > 0.0) || !std::isfinite(it->dt)) return hfail(h, VBC_ERR_ARG, "dt must be > 0");
     if (it->kind == VBC_LANGEVIN && (!(it->gamma >= 0.0) || !(it->kT >= 0.0)))
         return hfail(h, VBC_ERR_ARG, "gamma and kT must be >= 0");
-    if (nsteps == 0) return VBC_OK;
-    VBC_LAYOUT(h, s);
+    return VBC_OK;
+}
+
+static StepArgs step_args(const vbc_integrator *it)
+{
     StepArgs st = no_step();
     st.kind = it->kind;
     st.dt = it->dt;
@@ -1202,6 +1172,33 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
     st.c1 = std::exp(-it->gamma * it->dt);
     st.c2s = std::sqrt(1.0 - st.c1 * st.c1) * std::sqrt(it->kT);
     st.seed = it->seed;
+    return st;
+}
+
+vbc_status vbc_step_prepare(vbc_handle h, int32_t nsteps, const vbc_integrator *it)
+{
+    if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
+    vbc_status r = check_integrator(h, nsteps, it);
+    if (r != VBC_OK) return r;
+    if (nsteps == 0 || !h->use_graphs || h->prof) return VBC_OK;
+    const StepArgs st = step_args(it);
+    hipGraphExec_t ge = nullptr;
+    if (nsteps <= CALL_GRAPH_MAX) VBC_TRY(h, get_graph(h, 1, nsteps, h->cur, st, &ge), "call graph");
+    else if (nsteps - 1 >= GRAPH_STEPS) VBC_TRY(h, get_graph(h, 0, GRAPH_STEPS, h->cur ^ 1, st, &ge), "step graph");
+    return VBC_OK;
+}
+
+vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s)
+{
+    if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
+    VBC_NEED_STATE(h);
+    {
+        vbc_status r0 = check_integrator(h, nsteps, it);
+        if (r0 != VBC_OK) return r0;
+    }
+    if (nsteps == 0) return VBC_OK;
+    VBC_LAYOUT(h, s);
+    const StepArgs st = step_args(it);
     vbc_status r = eval_missing(h, st, s);
     if (r != VBC_OK) return r;
     const bool graphs = h->use_graphs && !h->prof;
@@ -1476,6 +1473,33 @@ vbc_status vbc_profile_read(vbc_handle h, hipStream_t s, double *ms, int64_t *la
         launches[k] = h->prof_n[k];
         h->prof_n[k] = 0;
     }
+    return VBC_OK;
+}
+
+vbc_status vbc_thermo(vbc_handle h, int32_t enable, hipStream_t s)
+{
+    if (!h) return fail(VBC_ERR_ARG, "NULL handle");
+    if ((enable != 0) != h->thermo) {
+        // the step graphs launch the force pass with or without the sums: recapture
+        for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
+    }
+    h->thermo = enable != 0;
+    VBC_TRY(h, launch_thermo_clear(h->B, h->P.nrep, s), "thermo reset");
+    return VBC_OK;
+}
+
+vbc_status vbc_thermo_read(vbc_handle h, hipStream_t s, double *out)
+{
+    if (!h || !out) return fail(VBC_ERR_ARG, "NULL argument");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
+    VBC_TRY(h, hipMemcpy(out, h->B.thermo, sizeof(double) * THERMO_WORDS * h->P.nrep, hipMemcpyDeviceToHost),
+            "thermo readback");
+    for (int r = 0; r < h->P.nrep; ++r)
+        if (!h->live[r])
+            for (int k = 0; k < THERMO_WORDS; ++k) out[(size_t)r * THERMO_WORDS + k] = 0.0;
+    VBC_TRY(h, launch_thermo_clear(h->B, h->P.nrep, s), "thermo reset");
+    VBC_TRY(h, hipStreamSynchronize(s), "sync");
     return VBC_OK;
 }
 

@@ -110,7 +110,11 @@ struct Buffers {
     uint32_t *bentries;         // [nbrick_tot] list entries of each brick at the last build
     unsigned long long *stamps; // [STAMP_CAP] device clock at the end of each stamped step
     unsigned long long *stamp_n; // [1] stamps written so far
+    double *thermo;             // [nrep][THERMO_WORDS] steps accumulated, last step's
+                                // {U, W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz}, their sums
 };
+
+constexpr int THERMO_WORDS = 17;
 
 constexpr int STAMP_CAP = 1 << 16;  // power of two
 
@@ -172,6 +176,8 @@ hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t 
 hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, bool thermo,
                         const StepArgs &st, double *F_out, double *e_out, hipStream_t s);
 hipError_t launch_reduce(const Buffers &B, const Launch &P, double *UW, hipStream_t s);
+hipError_t launch_thermo_acc(const Buffers &B, const Launch &P, hipStream_t s);
+hipError_t launch_thermo_clear(const Buffers &B, int nrep, hipStream_t s);
 hipError_t launch_kick_drift(const Buffers &B, const Launch &P, int cur, const StepArgs &st,
                              hipStream_t s);
 hipError_t launch_export_nlist(const Buffers &B, const Launch &P, int rep, int nbrick,

@@ -1098,6 +1098,83 @@ __device__ __forceinline__ void load_pairs(const RepDev &R, PairR<Real> *pt)
     }
 }
 
+// One term of eq. (counter) in FP64: omega(r, r_l, r_h) = (1 - u^2)^2 with
+// u = (r - r_l)/(r_h - r_l), exactly 1 inside r_l and 0 beyond r_h.
+__device__ __forceinline__ double count_term64(double r2, const PairDev &p)
+{
+    if (r2 <= p.rl2) return 1.0;
+    if (r2 >= p.rh2) return 0.0;
+    const double u = (sqrt(r2) - p.r_l) * p.inv_dw;
+    const double q = 1.0 - u * u;
+    return q * q;
+}
+
+// With FP32 pair arithmetic a particle is listed for an FP64 recount when its FP32 count
+// lies within this margin of a switching window (the FP32 count is within about 1e-5 of
+// the exact one), so that every particle whose exact count lies inside a window is listed.
+constexpr double COUNT_MARGIN = 1e-4;
+
+// Counts in FP64 of the particles the FP32 count pass listed (brick b, its first nw
+// entries of wlst): their switching factor s and dU/dn depend steeply on n (eq. (Psi),
+// eq. (Psidelta)), so the count is summed again from the FP64 positions, gathered through
+// the brick's staging map, instead of the FP32 staged ones (whose rounding would move each
+// count term by up to about 3e-6).  One group of eight lanes per particle, one list entry
+// per lane of each 16-byte chunk; the eight partial sums are added in a fixed order.
+// Writes n (FP64), s (or n with several types) and, if asked, the caller-order count.
+template <class Real, bool MULTI>
+__device__ void recount_window(const Buffers &B, const Launch &P, const RepDev &R, int b,
+                               int64_t base, int nw, const double *__restrict__ X,
+                               double *__restrict__ n_out)
+{
+    using R2 = typename V2<Real>::t;
+    const int g = threadIdx.x / CHUNK, e = threadIdx.x % CHUNK, ng = blockDim.x / CHUNK;
+    const int64_t S_ = P.nslots;
+    const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
+    const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
+    const bool xr = R.excl_span > 0;
+    const double L0 = R.L[0], L1 = R.L[1], L2 = R.L[2];
+    const PairDev p0 = R.pair[0];
+    R2 *sA = (R2 *)B.sA;
+    for (int k = g; k < nw; k += ng) {
+        const int t = B.wlst[base + k];
+        const int64_t i = base + t;
+        const double xi0 = X[i], xi1 = X[S_ + i], xi2 = X[2 * S_ + i];
+        const int ti = MULTI ? B.type[i] : 0;
+        const int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
+        double acc = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            const uint4 q = B.nl[(size_t)c * S_ + i];
+            const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
+            int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+            int ex = 0;
+            if (MULTI && xr) {
+                ex = u >> 15;
+                u &= 0x7fff;
+            }
+            if (u == P.stage_cap) continue;  // padding of the last chunk
+            const int src = sm[u], w = wm[u];
+            const double dx = xi0 - (X[src] + L0 * (double)unpack_w(w, 0));
+            const double dy = xi1 - (X[S_ + src] + L1 * (double)unpack_w(w, 1));
+            const double dz = xi2 - (X[2 * S_ + src] + L2 * (double)unpack_w(w, 2));
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            if (MULTI) {
+                const int tj = B.type[src];
+                if (ex || !((R.mask[ti] >> tj) & 1u)) continue;
+                acc += count_term64(r2, R.pair[ti * MAXT + tj]);
+            } else {
+                acc += count_term64(r2, p0);
+            }
+        }
+#pragma unroll
+        for (int o = CHUNK / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, CHUNK);
+        if (e == 0) {
+            B.nd[i] = acc;
+            sA[i] = R2{MULTI ? (Real)acc : (Real)omega_d64(acc, p0.x1, p0.x2), Real(0)};
+            if (n_out) n_out[R.o_off + B.tag[i]] = acc;
+        }
+    }
+}
+
 // STATS: also count the ordered pairs inside the interaction cutoff (the pair-evaluation
 // statistic); the step loop samples it on one step in eight.
 template <class Real, bool MULTI, bool STATS>
@@ -1197,16 +1274,19 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         evals += (unsigned long long)inside;
         B.nd[i] = n;
         bool win = false;
+        // with FP32 pair arithmetic the window is widened by the margin: the particles
+        // listed get their counts again in FP64 below, before anything reads them
+        const double mg = sizeof(Real) == 4 ? COUNT_MARGIN : 0.0;
         if (MULTI) {
             // the switching factor depends on the pair: keep the count itself
             sA[i] = R2{(Real)n, Real(0)};
             for (int u = 0; u < R.ntypes; ++u) {
                 const PairDev &pd = R.pair[ti * MAXT + u];
-                if (pd.attract && n > pd.x1 && n < pd.x2) win = true;
+                if (pd.attract && n > pd.x1 - mg && n < pd.x2 + mg) win = true;
             }
         } else {
             sA[i] = R2{(Real)omega_d64(n, wx1, wx2), Real(0)};
-            win = watt && n > wx1 && n < wx2;
+            win = watt && n > wx1 - mg && n < wx2 + mg;
         }
         // the dU/dn pass visits only these: list them compactly in the brick's slots
         if (win) B.wlst[S.base + atomicAdd(&nwin, 1)] = (uint16_t)t;
@@ -1217,6 +1297,11 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
         if ((threadIdx.x % VBC_WAVE) == 0 && evals) atomicAdd(&ev_sum, evals);
     }
     __syncthreads();
+    if (sizeof(Real) == 4) {
+        // the listed entries are in global memory, written by this workgroup before the barrier
+        const int nwv = nwin;
+        if (nwv > 0) recount_window<Real, MULTI>(B, P, R, b, S.base, nwv, X, n_out);
+    }
     if (threadIdx.x == 0) {
         B.wcnt[b] = nwin;
         if (STATS) B.bevals[b] += ev_sum;  // this workgroup is the only writer of brick b
@@ -1694,11 +1779,11 @@ __global__ void k_kick_drift(Buffers B, Launch P, int cur, StepArgs st)
         atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
 }
 
-// Per-replica totals from the per-brick partial sums, in brick order.
-__global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
+// Sum of the per-brick energy/virial partial sums of replica R over its bricks, in a fixed
+// order (strided per thread, then waves, then the wave totals in order); the result is
+// valid in threads 0..7 (one component each).
+__device__ __forceinline__ double replica_sum(const Buffers &B, const RepDev &R)
 {
-    int r = blockIdx.x;
-    const RepDev &R = B.reps[r];
     __shared__ double red[8][1024 / VBC_WAVE];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < R.nbrick; b += blockDim.x)
@@ -1709,11 +1794,41 @@ __global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
         if (ln == 0) red[k][wv] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 8) {
-        double s = 0.0;
+    double s = 0.0;
+    if (threadIdx.x < 8)
         for (int w = 0; w < (int)(blockDim.x / VBC_WAVE); ++w) s += red[threadIdx.x][w];
-        UW[r * 8 + threadIdx.x] = s;
+    return s;
+}
+
+// Per-replica totals from the per-brick partial sums, in brick order.
+__global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
+{
+    int r = blockIdx.x;
+    const RepDev &R = B.reps[r];
+    const double s = replica_sum(B, R);
+    if (threadIdx.x < 8) UW[r * 8 + threadIdx.x] = s;
+}
+
+// After a force pass with the sums on: each live replica's energy and virial of this step
+// (kept as the last step's) added to its running sums, and its step count raised by one.
+// A slot is live when its first brick is owned by it (retired descriptors stay behind).
+__global__ void k_thermo_acc(Buffers B, int nrep)
+{
+    const int r = blockIdx.x;
+    const RepDev &R = B.reps[r];
+    if (R.nbrick <= 0 || B.brick_rep[R.b_off] != r) return;
+    const double s = replica_sum(B, R);
+    if (threadIdx.x < 8) {
+        double *T = B.thermo + (size_t)r * THERMO_WORDS;
+        T[1 + threadIdx.x] = s;
+        T[9 + threadIdx.x] += s;
+        if (threadIdx.x == 0) T[0] += 1.0;
     }
+}
+
+__global__ void k_thermo_clear(Buffers B, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) B.thermo[i] = 0.0;
 }
 
 // Export the list of one replica as tag pairs (inspection and tests).
@@ -2522,6 +2637,19 @@ hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, b
         if (multi) launch_force_t<float, true>(B, P, cur, mode, thermo, st, F_out, e_out, s);
         else launch_force_t<float, false>(B, P, cur, mode, thermo, st, F_out, e_out, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_thermo_acc(const Buffers &B, const Launch &P, hipStream_t s)
+{
+    k_thermo_acc<<<P.nrep, 256, 0, s>>>(B, P.nrep);
+    return hipGetLastError();
+}
+
+hipError_t launch_thermo_clear(const Buffers &B, int nrep, hipStream_t s)
+{
+    const int n = nrep * THERMO_WORDS;
+    k_thermo_clear<<<blocks_for(n, 256), 256, 0, s>>>(B, n);
     return hipGetLastError();
 }
 

@@ -28,18 +28,27 @@ from . import workloads as W
 
 @dataclass
 class ServerConfig:
-    budget_bytes: int = 2 << 30      # HBM the live replicas may occupy
+    budget_bytes: int = 2 << 30      # HBM the live replicas of the main pool may occupy
     max_replicas: int = 64
     max_particles: int = 1 << 21
     precision: str = "fp32"
     steps_per_tick: int = 8
-    rho_max: float = 0.3             # densest request the pool is laid out for
+    rho_max: float = 0.3             # densest request the main pool is laid out for
+    # a request whose local density outgrows the main pool's layout (it condenses), or that
+    # trips any other error flag, is evicted and run again from its initial state in a
+    # second pool laid out for local densities up to dense_rho_max
+    dense_rho_max: float = 1.0
+    dense_budget_bytes: int = 1 << 30
+    dense_max_replicas: int = 16
+    dense_max_particles: int = 1 << 19
+    max_attempts: int = 2            # attempts per request (main pool, then dense pool)
+    check_every: int = 16            # ticks between reads of the running requests' flags
     n_range: tuple = (1_000, 200_000)
     skin: float = 0.4
     integrator: dict = field(default_factory=lambda: dict(integrator="langevin", dt=0.005,
                                                           kT=1.0, gamma=0.1, seed=2024))
     max_inflight: int = 6            # step launches the host may run ahead of the GPU
-    max_active: int = 0              # 0 = no limit beyond the pool; 1 = one at a time
+    max_active: int = 0              # 0 = no limit beyond the pools; 1 = one at a time
     brick: int = 0                   # 0 = the tuned choice if cached, else the library's
     block: int = 0
 
@@ -51,10 +60,11 @@ def request_desc(req, skin=0.4):
                         seed=req["seed"])
 
 
-def layout_for(cfg: ServerConfig):
+def layout_for(cfg: ServerConfig, rho_max=None):
     """List length and staging capacity that cover every request size at the design
     density (the largest automatic choice over a log grid of sizes), the range of
     slots-per-brick such requests need, and the smallest workspace bytes per slot."""
+    rho = cfg.rho_max if rho_max is None else rho_max
     k_max = stage_cap = bcap_max = 0
     bcap_min = 1 << 30
     # a log grid of sizes, plus the sizes just below each change of the cell count per
@@ -67,15 +77,71 @@ def layout_for(cfg: ServerConfig):
     grid = np.unique(grid.astype(int))
     descs = [request_desc(dict(N=int(N), f=1.0, E_a=5.0, rho=cfg.rho_max, seed=0), cfg.skin)
              for N in grid]
+    extra = dict(rho_max=rho) if rho > cfg.rho_max else {}
     for d in descs:
-        fp = _vbc.footprint(d, cfg.precision, brick=cfg.brick)
+        fp = _vbc.footprint(d, cfg.precision, brick=cfg.brick, **extra)
         k_max, stage_cap = max(k_max, fp["k_max"]), max(stage_cap, fp["stage_cap"])
         bcap_max, bcap_min = max(bcap_max, fp["bcap"]), min(bcap_min, fp["bcap"])
     per_slot = min(fp["bytes"] / fp["slots"] for fp in
-                   (_vbc.footprint(d, cfg.precision, k_max=k_max, stage_cap=stage_cap, brick=cfg.brick)
+                   (_vbc.footprint(d, cfg.precision, k_max=k_max, stage_cap=stage_cap, brick=cfg.brick, **extra)
                     for d in descs))
     return dict(k_max=k_max, stage_cap=stage_cap, bcap_max=bcap_max, bcap_min=bcap_min,
-                bytes_per_slot=per_slot)
+                bytes_per_slot=per_slot, rho_max=rho)
+
+
+class Lane:
+    """One replica pool of the server with its layout, capacity, occupancy and step
+    stamps."""
+
+    def __init__(self, srv, name, rho_max, budget, max_replicas, max_particles):
+        c = srv.cfg
+        self.name, self.cfg, self.torch = name, c, srv.torch
+        lay = layout_for(c, rho_max)
+        self.rho_max = rho_max
+        self.k_max, self.stage_cap = lay["k_max"], lay["stage_cap"]
+        self.budget, self.max_replicas, self.max_particles = budget, max_replicas, max_particles
+        # capacities that the byte budget reaches first: a replica's slots cost at least
+        # bytes_per_slot each, and its bricks hold at least bcap_min slots
+        max_slots = int(budget / lay["bytes_per_slot"]) + 1
+        max_bricks = max_slots // lay["bcap_min"] + max_replicas
+        caps = dict(max_replicas=max_replicas, max_types=1, max_particles=max_particles,
+                    max_slots=max(max_slots, max_particles), max_bricks=max_bricks,
+                    max_cells=max_bricks * 64, max_bcap=max(lay["bcap_max"], 64), chains=False)
+        self.pool = _vbc.Pool(caps, precision=c.precision, k_max=self.k_max, stage_cap=self.stage_cap,
+                              brick=c.brick, block=c.block, rho_max=rho_max if rho_max > c.rho_max else 0.0,
+                              device=srv.device)
+        self.reset()
+
+    def reset(self):
+        self.active = {}      # slot -> [request index, ticks left, first step, flags seen]
+        self.used_bytes = self.used_particles = 0
+        self.gstep = 0
+        self.stamps = []
+        self.busy = set()     # first step of a tick preceded by admissions or a sync
+        self.since_read = 0
+        self.ticks_since_check = 0
+
+    def footprint(self, req):
+        extra = dict(rho_max=self.rho_max) if self.rho_max > self.cfg.rho_max else {}
+        return _vbc.footprint(request_desc(req, self.cfg.skin), self.cfg.precision,
+                              k_max=self.k_max, stage_cap=self.stage_cap, brick=self.cfg.brick,
+                              **extra)["bytes"]
+
+    def warm(self):
+        """Capture the step graphs (both buffer parities) on a tiny replica."""
+        c = self.cfg
+        req = dict(N=c.n_range[0], f=2.0, E_a=5.0, rho=c.rho_max, seed=1)
+        d = request_desc(req, c.skin)
+        x = W.uniform_positions(req["N"], d["L"][0], 1)
+        r = self.pool.admit(d, x)
+        for n in (c.steps_per_tick, c.steps_per_tick + 1, c.steps_per_tick):
+            self.pool.step(n, **c.integrator)
+        self.pool.check()
+        self.pool.retire(r)
+
+    def drain_stamps(self):
+        self.stamps.append(self.pool.stamps_read())
+        self.since_read = 0
 
 
 class Server:
@@ -90,185 +156,215 @@ class Server:
             best = tune.lookup(tune.pool_key(c))
             if best:
                 c.brick, c.block = best["brick"], best["block"]
-        lay = layout_for(c)
-        self.k_max, self.stage_cap = lay["k_max"], lay["stage_cap"]
-        # capacities that the byte budget reaches first: a replica's slots cost at least
-        # bytes_per_slot each, and its bricks hold at least bcap_min slots
-        max_slots = int(c.budget_bytes / lay["bytes_per_slot"]) + 1
-        max_bricks = max_slots // lay["bcap_min"] + c.max_replicas
-        caps = dict(max_replicas=c.max_replicas, max_types=1, max_particles=c.max_particles,
-                    max_slots=max(max_slots, c.max_particles), max_bricks=max_bricks,
-                    max_cells=max_bricks * 64, max_bcap=max(lay["bcap_max"], 64), chains=False)
-        self.pool = _vbc.Pool(caps, precision=c.precision, k_max=self.k_max,
-                              stage_cap=self.stage_cap, brick=c.brick, block=c.block, device=device)
-        self.device = self.pool.device
+        self.device = torch.device(device) if isinstance(device, str) else device
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.lanes = [Lane(self, "main", c.rho_max, c.budget_bytes, c.max_replicas, c.max_particles)]
+        if c.max_attempts > 1:
+            self.lanes.append(Lane(self, "dense", c.dense_rho_max, c.dense_budget_bytes,
+                                   c.dense_max_replicas, c.dense_max_particles))
+        self.pool = self.lanes[0].pool
+        self.k_max, self.stage_cap = self.lanes[0].k_max, self.lanes[0].stage_cap
         self.stream = torch.cuda.current_stream(self.device)
-        self._warm()
-
-    def _warm(self):
-        """Capture the step graphs (both buffer parities) on a tiny replica."""
-        c = self.cfg
-        req = dict(N=c.n_range[0], f=2.0, E_a=5.0, rho=c.rho_max, seed=1)
-        d = request_desc(req, c.skin)
-        x = W.uniform_positions(req["N"], d["L"][0], 1)
-        r = self.pool.admit(d, x)
-        for n in (c.steps_per_tick, c.steps_per_tick + 1, c.steps_per_tick):
-            self.pool.step(n, **c.integrator)
-        self.pool.check()
-        self.pool.retire(r)
-        self.torch.cuda.synchronize(self.device)
+        for ln in self.lanes:
+            ln.warm()
+        torch.cuda.synchronize(self.device)
 
     def footprint(self, req):
-        return _vbc.footprint(request_desc(req, self.cfg.skin), self.cfg.precision,
-                              k_max=self.k_max, stage_cap=self.stage_cap, brick=self.cfg.brick)["bytes"]
+        return self.lanes[0].footprint(req)
 
     def run(self, requests, arrivals=None, keep_results=False):
         """Serve `requests` (dicts with N, f, E_a, rho, seed, steps and device tensors x, v
         of shape (N, 3)); arrivals[k] = seconds after the start at which request k
         arrives (None: all at once).  Returns per-request timings, per-step latencies and
-        totals."""
-        torch, cfg, pool = self.torch, self.cfg, self.pool
+        totals over the requests that completed without an error flag.
+
+        The running requests' flags are read every `check_every` ticks and whenever one
+        finishes (each read synchronises and clears the flags, so they are kept per request
+        until it leaves).  A request with an error flag (list or staging overflow, a
+        non-finite coordinate, a particle lost between list builds) is evicted at once and,
+        while attempts are left, queued again from its initial state for the dense pool;
+        otherwise it is marked failed.  Failed requests and evicted attempts count in no
+        throughput or latency figure."""
+        torch, cfg = self.torch, self.cfg
         S = cfg.steps_per_tick
+        lanes = self.lanes
         n_req = len(requests)
         arr = np.zeros(n_req) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
         order = np.argsort(arr, kind="stable")
-        fps = [self.footprint(q) for q in requests]
+        fps = [[ln.footprint(q) for q in requests] for ln in lanes]
         for k, q in enumerate(requests):
             if q["steps"] % S:
                 raise ValueError("request steps must be a multiple of steps_per_tick")
-            if fps[k] > cfg.budget_bytes or q["N"] > cfg.max_particles:
+            if fps[0][k] > cfg.budget_bytes or q["N"] > cfg.max_particles:
                 raise ValueError(f"request {k} can never fit the pool")
+        for ln in lanes:
+            ln.reset()
         ev_start = torch.cuda.Event(enable_timing=True)
-        ticks = []                      # (event, first global step)
-        queue = deque()
-        active = {}                     # slot -> [request index, ticks left, first step]
-        used_bytes = used_particles = 0
+        ticks = []                      # (event, lane index)
+        queues = [deque() for _ in lanes]
         nxt = 0
-        gstep = 0
-        stamps = []
         admit_t = np.full(n_req, np.nan)
         first_step = np.zeros(n_req, dtype=np.int64)
-        done_tick = np.zeros(n_req, dtype=np.int64)
+        lane_of = np.zeros(n_req, dtype=np.int64)
+        attempts = np.zeros(n_req, dtype=np.int64)
+        done_tick = np.full(n_req, -1, dtype=np.int64)
+        failed = np.zeros(n_req, dtype=bool)
+        final_flags = np.zeros(n_req, dtype=np.int64)  # flags of the run that completed
         results = [None] * n_req
-        flagged = []
-        busy_steps = set()              # first step of a tick preceded by admissions or a sync
+        flagged = []                    # (request, lane, flags, what happened)
 
-        def drain_stamps():
-            stamps.append(pool.stamps_read())
+        def read_flags(li, finished):
+            """Read lane li's flags, keep them per request, evict the requests with an
+            error, and retire the finished ones."""
+            ln = lanes[li]
+            ln.busy.add(ln.gstep)
+            st, flags = ln.pool.check(raise_on_error=False)
+            for r, a in ln.active.items():
+                a[3] |= flags[r] & ~_vbc.FLAG_REBUILD
+            for r in list(ln.active):
+                k, left, g0, fl = ln.active[r]
+                if fl:
+                    what = "failed"
+                    if attempts[k] < cfg.max_attempts and li + 1 < len(lanes):
+                        what = f"evicted to the {lanes[li + 1].name} pool"
+                        queues[li + 1].appendleft(k)
+                        lane_of[k] = li + 1
+                    else:
+                        failed[k] = True
+                    flagged.append((k, ln.name, int(fl), what))
+                elif r in finished:
+                    final_flags[k] = fl
+                    if keep_results:
+                        x, v = ln.pool.get_state(r)
+                        results[k] = (x.clone(), v.clone())
+                    done_tick[k] = len(ticks) - 1
+                else:
+                    continue
+                ln.pool.retire(r)
+                ln.used_bytes -= fps[li][k]
+                ln.used_particles -= requests[k]["N"]
+                del ln.active[r]
+            ln.ticks_since_check = 0
 
-        pool.stamps(True)
+        for ln in lanes:
+            ln.pool.stamps(True)
         ev_start.record(self.stream)
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
-        since_read = 0
-        while nxt < n_req or queue or active:
+        while nxt < n_req or any(queues) or any(ln.active for ln in lanes):
             now = time.perf_counter() - t0
             while nxt < n_req and arr[order[nxt]] <= now:
-                queue.append(int(order[nxt]))
+                queues[0].append(int(order[nxt]))
                 nxt += 1
-            # admission: FIFO, while the head fits
-            while queue:
-                k = queue[0]
-                q = requests[k]
-                if cfg.max_active and len(active) >= cfg.max_active:
-                    break
-                if (len(active) >= cfg.max_replicas or used_bytes + fps[k] > cfg.budget_bytes
-                        or used_particles + q["N"] > cfg.max_particles):
-                    break
-                try:
-                    r = pool.admit(request_desc(q, cfg.skin), q["x"], q["v"])
-                except _vbc.VBCError as e:
-                    if e.status != _vbc.VBC_ERR_CAPACITY:
-                        raise
-                    break  # no contiguous range now: wait for a retirement
-                queue.popleft()
-                active[r] = [k, q["steps"] // S, gstep]
-                admit_t[k] = time.perf_counter() - t0
-                busy_steps.add(gstep)
-                first_step[k] = gstep
-                used_bytes += fps[k]
-                used_particles += q["N"]
-            if not active:
+            # admission: FIFO per pool, while the head fits
+            for li, ln in enumerate(lanes):
+                q_ = queues[li]
+                while q_:
+                    k = q_[0]
+                    q = requests[k]
+                    if cfg.max_active and sum(len(x.active) for x in lanes) >= cfg.max_active:
+                        break
+                    if (len(ln.active) >= ln.max_replicas or ln.used_bytes + fps[li][k] > ln.budget
+                            or ln.used_particles + q["N"] > ln.max_particles):
+                        break
+                    try:
+                        r = ln.pool.admit(request_desc(q, cfg.skin), q["x"], q["v"])
+                    except _vbc.VBCError as e:
+                        if e.status != _vbc.VBC_ERR_CAPACITY:
+                            raise
+                        break  # no contiguous range now: wait for a retirement
+                    q_.popleft()
+                    attempts[k] += 1
+                    ln.active[r] = [k, q["steps"] // S, ln.gstep, 0]
+                    if np.isnan(admit_t[k]):
+                        admit_t[k] = time.perf_counter() - t0
+                    ln.busy.add(ln.gstep)
+                    first_step[k] = ln.gstep
+                    ln.used_bytes += fps[li][k]
+                    ln.used_particles += q["N"]
+            if not any(ln.active for ln in lanes):
                 if nxt < n_req:
                     time.sleep(max(0.0, min(arr[order[nxt]] - (time.perf_counter() - t0), 0.01)))
                 continue
-            pool.step(S, **cfg.integrator)
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(self.stream)
-            ticks.append((ev, gstep))
-            gstep += S
-            since_read += S
-            finished = []
-            for r, a in active.items():
-                a[1] -= 1
-                if a[1] == 0:
-                    finished.append(r)
-            if finished:
-                busy_steps.add(gstep)
-                st, flags = pool.check(raise_on_error=False)
-                for r in finished:
-                    k = active[r][0]
-                    if flags[r] & ~_vbc.FLAG_REBUILD:
-                        flagged.append((k, flags[r]))
-                    if keep_results:
-                        x, v = pool.get_state(r)
-                        results[k] = (x.clone(), v.clone())
-                    pool.retire(r)
-                    done_tick[k] = len(ticks) - 1
-                    used_bytes -= fps[k]
-                    used_particles -= requests[k]["N"]
-                    del active[r]
-            if since_read > (1 << 15):
-                drain_stamps()
-                since_read = 0
+            for li, ln in enumerate(lanes):
+                if not ln.active:
+                    continue
+                ln.pool.step(S, **cfg.integrator)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.stream)
+                ticks.append((ev, li))
+                ln.gstep += S
+                ln.since_read += S
+                ln.ticks_since_check += 1
+                finished = set()
+                for r, a in ln.active.items():
+                    a[1] -= 1
+                    if a[1] == 0:
+                        finished.add(r)
+                if finished or ln.ticks_since_check >= cfg.check_every:
+                    read_flags(li, finished)
+                if ln.since_read > (1 << 15):
+                    ln.drain_stamps()
             if len(ticks) > cfg.max_inflight:
                 ticks[-cfg.max_inflight - 1][0].synchronize()
-        drain_stamps()
-        pool.stamps(False)
+        for ln in lanes:
+            ln.drain_stamps()
+            ln.pool.stamps(False)
         torch.cuda.synchronize(self.device)
         t_tick = np.array([ev_start.elapsed_time(ev) * 1e-3 for ev, _ in ticks])
-        st = np.concatenate(stamps) if stamps else np.zeros(0)
-        if len(st) != gstep:
-            raise RuntimeError(f"expected {gstep} step stamps, got {len(st)}")
+        lane_stamps = []
+        for ln in lanes:
+            st = np.concatenate(ln.stamps) if ln.stamps else np.zeros(0)
+            if len(st) != ln.gstep:
+                raise RuntimeError(f"{ln.name} pool: expected {ln.gstep} step stamps, got {len(st)}")
+            lane_stamps.append(st)
         # per-step latency: interval between a request's successive step completions
+        ok = [k for k in range(n_req) if not failed[k]]
         lat, quiet = [], []
-        busy = np.zeros(len(st) + 1, dtype=bool)
-        for g in busy_steps:
-            if g < busy.size:
-                busy[g] = True
-        for k, q in enumerate(requests):
-            g0 = first_step[k]
+        for k in ok:
+            q, li, g0 = requests[k], lane_of[k], first_step[k]
+            st = lane_stamps[li]
+            busy = np.zeros(len(st) + 1, dtype=bool)
+            for g in lanes[li].busy:
+                if g < busy.size:
+                    busy[g] = True
             d = np.diff(st[g0:g0 + q["steps"]])
             lat.append(d)
             quiet.append(d[~busy[g0 + 1:g0 + q["steps"]]])  # interval ending at step g0 + 1 + m
         lat = np.concatenate(lat) if lat else np.zeros(0)
         quiet = np.concatenate(quiet) if quiet else np.zeros(0)
-        done = t_tick[done_tick]
-        req_lat = done - arr
-        makespan = float(done.max())
-        n_steps = sum(q["steps"] for q in requests)
-        p_steps = sum(q["steps"] * q["N"] for q in requests)
+        done = t_tick[done_tick[ok]] if ok else np.zeros(0)
+        req_lat = done - arr[ok]
+        makespan = float(t_tick.max()) if len(t_tick) else 0.0
+        n_steps = sum(requests[k]["steps"] for k in ok)
+        p_steps = sum(requests[k]["steps"] * requests[k]["N"] for k in ok)
+        pct = lambda a, p: float(np.percentile(a, p)) if a.size else None
         return dict(
             makespan_s=makespan,
-            requests_per_s=n_req / makespan,
-            request_steps_per_s=n_steps / makespan,
-            particle_steps_per_s=p_steps / makespan,
-            step_latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
-                                 p99=1e3 * float(np.percentile(lat, 99)),
+            requests_per_s=len(ok) / makespan if makespan else 0.0,
+            request_steps_per_s=n_steps / makespan if makespan else 0.0,
+            particle_steps_per_s=p_steps / makespan if makespan else 0.0,
+            step_latency_ms=dict(p50=1e3 * pct(lat, 50), p99=1e3 * pct(lat, 99),
                                  mean=1e3 * float(lat.mean()), n=int(lat.size)),
             # the same over the steps whose tick did not start with admissions or a host sync
             step_latency_ms_between_events=dict(
-                p50=1e3 * float(np.percentile(quiet, 50)) if quiet.size else None,
-                p99=1e3 * float(np.percentile(quiet, 99)) if quiet.size else None,
+                p50=1e3 * pct(quiet, 50) if quiet.size else None,
+                p99=1e3 * pct(quiet, 99) if quiet.size else None,
                 n=int(quiet.size)),
-            request_latency_s=dict(p50=float(np.percentile(req_lat, 50)),
-                                   p99=float(np.percentile(req_lat, 99)),
-                                   max=float(req_lat.max())),
+            request_latency_s=dict(p50=pct(req_lat, 50), p99=pct(req_lat, 99),
+                                   max=float(req_lat.max()) if req_lat.size else None),
             queue_wait_s=dict(p50=float(np.nanpercentile(admit_t - arr, 50)),
                               p99=float(np.nanpercentile(admit_t - arr, 99))),
-            global_steps=int(gstep),
-            mean_live=float(n_steps / max(gstep, 1)),
+            global_steps=int(sum(ln.gstep for ln in lanes)),
+            mean_live=float(sum(requests[k]["steps"] for k in range(n_req)) / max(lanes[0].gstep, 1)),
+            completed=len(ok), failed=int(failed.sum()),
+            # completed requests whose counted run raised an error flag (kept per request over
+            # every flag read of its run): zero unless eviction failed to catch one
+            flagged_in_figures=int(sum(1 for k in ok if final_flags[k])),
+            rerun_in_dense_pool=int(sum(1 for k in ok if lane_of[k] > 0)),
             flagged=flagged,
+            lane_of=lane_of.tolist(),
             results=results if keep_results else None,
         )
 
@@ -311,13 +407,21 @@ def serving_benchmark(n=256, steps=1000, seed=5, load=0.8, cfg=None, log=None):
     single = srv.run(reqs, arrivals)
     srv.cfg.max_active = 0
     say(f"[serve] one at a time: {single['requests_per_s']:.1f} req/s")
-    strip = lambda d: {k: v for k, v in d.items() if k not in ("results", "flagged")}
+    strip = lambda d: {k: v for k, v in d.items() if k not in ("results", "flagged", "lane_of")}
     return dict(requests=n, steps_per_request=steps, arrival_rate_per_s=rate, load=load,
                 steps_per_tick=cfg.steps_per_tick, budget_bytes=cfg.budget_bytes,
                 max_replicas=cfg.max_replicas, max_particles=cfg.max_particles,
+                dense_pool=dict(rho_max=cfg.dense_rho_max, budget_bytes=cfg.dense_budget_bytes,
+                                max_replicas=cfg.dense_max_replicas),
                 mean_N=float(np.mean([q["N"] for q in reqs])),
                 saturated=strip(sat), batched=strip(batched), one_at_a_time=strip(single),
-                flagged=len(sat["flagged"]) + len(batched["flagged"]) + len(single["flagged"]),
+                # requests counted in the figures although an error flag was raised for them:
+                # none by construction (a flagged attempt is evicted, see Server.run)
+                flagged=sum(r["flagged_in_figures"] for r in (sat, batched, single)),
+                evictions=len(sat["flagged"]) + len(batched["flagged"]) + len(single["flagged"]),
+                failed=sat["failed"] + batched["failed"] + single["failed"],
+                flag_events=[dict(request=k, pool=p, flags=f, action=a)
+                             for r in (sat, batched, single) for (k, p, f, a) in r["flagged"]][:32],
                 speedup_throughput=batched["particle_steps_per_s"] / single["particle_steps_per_s"])
 
 

@@ -96,12 +96,73 @@ def saturation_sweep(fs=(1, 2, 3, 4, 5, 6), beta_Ea=(1.0, 2.0, 4.0, 6.0, 8.0), N
                 results=out)
 
 
+STABILITY_EA = (0.1, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 5.0)
+
+
+def stability_sweep(E_as=STABILITY_EA, geometries=("standard", "partial", "blind", "none"), N=1000,
+                    rho=0.05, steps=200_000, sample_every=1_000, dt=0.01, precision="fp32", seed=41,
+                    rho_max=3.0, log=None):
+    """The stability study of Section 6.2 (Fig. 12): the four counter geometries of
+    workloads.stability_sets (standard VBC(1.5, 2.0) with f = 12, partial coverage
+    r_h = 1.25 with f = 0.5, blind coverage r_h = 1.0 with f = 0.001, and no correction,
+    f = 1000) at N = 1000, density 0.05, E_r = 20, r_r = 1, r_a = 1.5, over a sweep of the
+    well depth E_a; Langevin kT = 1, gamma = 0.1, dt = 0.01.  Every (geometry, E_a) pair is
+    a replica of one handle laid out for the collapsed droplets of the uncorrected system
+    (local densities up to rho_max, bricks of 2^3 cells to keep that staging in LDS).  Over
+    the second half of the run, sampled every `sample_every` steps: the mean number of
+    neighbours within r_a per particle (contacts, panel (a)) and within r_r (core
+    penetrations, panel (b)), with the interquartile range across frames."""
+    say = log or (lambda m: None)
+    conds = [(g, e) for g in geometries for e in E_as]
+    L = W.box_length(N, rho)
+    reps, xs, vs = [], [], []
+    for k, (g, e) in enumerate(conds):
+        reps.append(_vbc.replica(N, L, W.stability_sets(e)[g], seed=k))
+        xs.append(W.uniform_positions(N, L, seed + k))
+        vs.append(W.maxwell_boltzmann(N, 1.0, seed + 100 + k))
+    s = _vbc.System(reps, precision=precision, rho_max=rho_max, brick=2)
+    s.set_state(np.concatenate(xs), np.concatenate(vs))
+    frames = {c: [] for c in conds}
+    done = 0
+    while done < steps:
+        s.step(sample_every, integrator="langevin", dt=dt, kT=1.0, gamma=0.1, seed=seed)
+        done += sample_every
+        if done > steps // 2:
+            _, _, sums = s.observables()
+            sums = sums.cpu().numpy()
+            for r, c in enumerate(conds):
+                frames[c].append((sums[r, 0] / N, sums[r, 2] / N))
+        if done % (10 * sample_every) == 0:
+            s.check()
+            say(f"[stability] {done}/{steps} steps")
+    s.check()
+    s.close()
+    out = {}
+    for c in conds:
+        h = np.array(frames[c])
+        out.setdefault(c[0], {})[f"{c[1]:g}"] = dict(
+            contacts=float(h[:, 0].mean()), contacts_iqr=[float(np.percentile(h[:, 0], 25)),
+                                                         float(np.percentile(h[:, 0], 75))],
+            penetrations=float(h[:, 1].mean()), penetrations_iqr=[float(np.percentile(h[:, 1], 25)),
+                                                                 float(np.percentile(h[:, 1], 75))])
+    return dict(workload=dict(N=N, rho=rho, E_r=20.0, r_r=1.0, r_a=1.5, steps=steps, dt=dt,
+                              precision=precision, integrator="Langevin kT=1 gamma=0.1",
+                              sampled="second half, every %d steps" % sample_every),
+                results=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=10_000)
     ap.add_argument("--steps", type=int, default=40_000)
+    ap.add_argument("--stability", action="store_true",
+                    help="run the stability sweep of the four counter geometries instead")
     a = ap.parse_args()
-    res = saturation_sweep(N=a.N, steps=a.steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    if a.stability:
+        res = stability_sweep(log=say)
+    else:
+        res = saturation_sweep(N=a.N, steps=a.steps, log=say)
     print(json.dumps(res), flush=True)
 
 

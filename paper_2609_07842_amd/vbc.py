@@ -31,7 +31,8 @@ EXPORTS = ("vbc_workspace_size", "vbc_create", "vbc_destroy", "vbc_last_error", 
            "vbc_replica_footprint", "vbc_pool_workspace_size", "vbc_pool_create", "vbc_admit",
            "vbc_retire", "vbc_replica_info", "vbc_stamps", "vbc_stamps_read", "vbc_tune_set",
            "vbc_observables", "vbc_cluster_scratch_size", "vbc_clusters", "vbc_bond_track_size",
-           "vbc_bond_track", "vbc_clusters_noalloc")
+           "vbc_bond_track", "vbc_clusters_noalloc", "vbc_step_prepare", "vbc_thermo",
+           "vbc_thermo_read")
 KERNEL_CLASSES = ("build", "count", "embed", "force", "kick", "reduce")
 
 
@@ -118,6 +119,9 @@ def lib():
             "vbc_cluster_scratch_size": [vp, C.POINTER(C.c_size_t)],
             "vbc_clusters": [vp, dp, C.c_size_t, dp, dp, dp, i32, vp],
             "vbc_clusters_noalloc": [vp, dp, dp, dp, i32, vp],
+            "vbc_step_prepare": [vp, i32, C.POINTER(Integrator)],
+            "vbc_thermo": [vp, i32, vp],
+            "vbc_thermo_read": [vp, vp, C.POINTER(C.c_double)],
             "vbc_bond_track_size": [vp, i32, C.POINTER(C.c_size_t)],
             "vbc_bond_track": [vp, dp, C.c_size_t, i32, i32, dp, i32, i64, dp, vp],
             "vbc_stamps_read": [vp, vp, C.POINTER(C.c_uint64), i64, C.POINTER(C.c_int64),
@@ -365,11 +369,34 @@ class _Handle:
         (slots, 5) as int64 tensors."""
         return BondTracker(self, max_partners, hist_len, bin_steps)
 
-    def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
+    @staticmethod
+    def _integrator(integrator, dt, kT, gamma, seed):
         it = Integrator()
         it.kind = NVE if integrator in ("nve", NVE) else LANGEVIN
         it.dt, it.kT, it.gamma, it.seed = float(dt), float(kT), float(gamma), int(seed)
+        return it
+
+    def step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
+        it = self._integrator(integrator, dt, kT, gamma, seed)
         self._ok(lib().vbc_step(self.h, int(nsteps), C.byref(it), self._stream()))
+
+    def prepare_step(self, nsteps, integrator="nve", dt=0.005, kT=1.0, gamma=0.1, seed=0):
+        """Capture the step graphs a step() call with these arguments would launch next
+        (vbc_step_prepare); launches nothing."""
+        it = self._integrator(integrator, dt, kT, gamma, seed)
+        self._ok(lib().vbc_step_prepare(self.h, int(nsteps), C.byref(it)))
+
+    def thermo(self, enable=True):
+        """Accumulate the energy and virial of every step (vbc_thermo); clears the sums."""
+        self._ok(lib().vbc_thermo(self.h, 1 if enable else 0, self._stream()))
+
+    def thermo_read(self):
+        """Per replica slot: steps accumulated, the last step's {U, W, W_xx, W_yy, W_zz,
+        W_xy, W_xz, W_yz} and their sums over those steps (then cleared)."""
+        out = (C.c_double * (17 * self.nslot))()
+        self._ok(lib().vbc_thermo_read(self.h, self._stream(), out))
+        a = np.frombuffer(out, dtype=np.float64).reshape(self.nslot, 17).copy()
+        return [dict(steps=int(r[0]), last=r[1:9].copy(), sum=r[9:17].copy()) for r in a]
 
     def check(self, raise_on_error=True):
         flags = (C.c_uint32 * self.nslot)()

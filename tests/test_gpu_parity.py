@@ -106,19 +106,11 @@ def test_fp32_mixed_parity(name, N, L, params):
     err_F = _normwise(F, ref["F"])
     print(f"  fp32 normwise force error {err_F:.2e}", flush=True)
     assert np.abs(n - ref["n"]).max() <= 1e-5
-    tol = 1e-5
-    if name == "window_heavy_f10":
-        # With counts inside the switching window almost everywhere, A_i = dU/dn_i is large
-        # and the forces depend steeply on the counts, hence on positions: the exact forces
-        # themselves move by ~7e-6 (normwise) when every coordinate is perturbed by the
-        # rounding of the FP32 staged positions (half an ulp at |x| < 8, 2.4e-7).  Bound the
-        # FP32 path by twice that sensitivity of the exact problem (and 1e-5 from below).
-        rng = np.random.default_rng(11)
-        xp = x + rng.uniform(-2.4e-7, 2.4e-7, size=x.shape)
-        sens = _normwise(oracle.evaluate(xp, L, params)["F"], ref["F"])
-        print(f"  exact problem's sensitivity to FP32 position rounding {sens:.2e}", flush=True)
-        tol = max(1e-5, 2.0 * sens)
-    assert err_F <= tol
+    # particles inside a switching window have their counts summed again in FP64
+    win = (ref["n"] > params["f"] - params["delta"]) & (ref["n"] < params["f"] - params["delta"] + 1)
+    if win.any():
+        assert np.abs(n[win] - ref["n"][win]).max() <= 1e-12
+    assert err_F <= 1e-5
     esc = np.abs(ref["e"]).sum()
     assert abs(UW[0, 0] - ref["U"]) <= 1e-5 * max(1.0, esc)
     assert abs(UW[0, 1] - ref["W"]) <= 1e-5 * max(1.0, np.abs(ref["W"]) + esc)
@@ -252,6 +244,30 @@ def test_trajectory_parity_fp64(kind):
     F, e, UW = s.force()
     Fr = oracle.evaluate(ref["x"], wl.L, wl.params)["F"]
     assert _normwise(F.cpu().numpy(), Fr) <= 1e-9
+
+
+def test_trajectory_parity_fp32_timed_kernel():
+    """The time step as the benchmark runs it (FP32 pair arithmetic, the integrator fused
+    into the force pass, whole-call step graph): 1000 particles at density 0.3, valency 2,
+    well depth 5, 50 BAOAB Langevin steps with the shared counter-based noise, against the
+    FP64 oracle's trajectory.  The FP32 forces are within about 3e-6 of the exact ones
+    (normwise), so over 50 steps of dt = 0.005 the positions may drift apart by about
+    dt^2 |dF| per step, amplified by the chaotic dynamics; the bound 2e-5 on every
+    coordinate (box edge 14.9) holds that with a margin, and the velocities are held to
+    2e-4 (thermal speed ~1)."""
+    wl = W.small_fluid()
+    s = _system(wl.N, wl.L, wl.params, precision="fp32")
+    s.set_state(wl.x, wl.v)
+    s.step(50, integrator="langevin", dt=0.005, kT=1.0, gamma=0.1, seed=13)
+    s.check()
+    x, v = (t.cpu().numpy() for t in s.get_state())
+    ref = oracle.run(wl.x, wl.v, wl.L, wl.params, 50, kind=oracle.LANGEVIN, dt=0.005, kT=1.0,
+                     gamma=0.1, seed=13)
+    dx = np.abs(_min_image(x - ref["x"], wl.L)).max()
+    dv = np.abs(v - ref["v"]).max()
+    print(f"[traj fp32] max |dx| {dx:.2e}, max |dv| {dv:.2e}", flush=True)
+    assert dx <= 2e-5
+    assert dv <= 2e-4
 
 
 def test_list_overflow_is_reported():

@@ -205,6 +205,50 @@ def test_sampled_parity_at_full_size(N, rho, f, nsample):
     assert np.abs(F.sum(axis=0)).max() <= 1e-5 * np.linalg.norm(F, axis=1).max() * np.sqrt(N)
 
 
+def test_sampled_parity_headline_after_steps():
+    """The headline fluid (N = 10^6, density 0.5, f = 4, FP32 pair arithmetic) after 500
+    Langevin steps of its benchmark trajectory, in the benchmark's launch configuration:
+    counts and forces of particles inside a switching window (their counts are summed again
+    in FP64), of their neighbours and of uniformly drawn particles against the oracle's local
+    evaluation at the GPU's own positions."""
+    from scipy.spatial import cKDTree
+    vbc = _vbc()
+    print("[sampled headline after 500 steps] N=1000000", flush=True)
+    wl = W.headline()
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32")
+    s.set_state(wl.x, wl.v)
+    s.step(500, integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=3)
+    s.check()
+    x = s.get_state()[0].cpu().numpy()
+    n = s.count().cpu().numpy()
+    F, e, UW = s.force()
+    s.check()
+    F = F.cpu().numpy()
+    x1 = wl.params["f"] - wl.params["delta"]
+    rng = np.random.default_rng(29)
+    win = np.nonzero((n > x1) & (n < x1 + 1.0))[0]
+    print(f"  {len(win)} particles inside the switching window", flush=True)
+    assert len(win) > 0
+    pick = rng.choice(win, size=min(16, len(win)), replace=False)
+    nb = set()
+    for row in cKDTree(x, boxsize=wl.L).query_ball_point(x[pick], 2.0):
+        nb.update(row)
+    nb = np.array(sorted(nb - set(pick.tolist())), dtype=np.int64)
+    nbs = rng.choice(nb, size=min(16, len(nb)), replace=False)
+    uni = rng.choice(wl.N, size=16, replace=False)
+    idx = np.unique(np.concatenate([pick, nbs, uni]))
+    ref = oracle.evaluate_subset(x, wl.L, wl.params, idx)
+    assert np.abs(n[idx] - ref["n"]).max() <= 1e-5
+    w = np.isin(idx, pick)
+    assert np.abs(n[idx][w] - ref["n"][w]).max() <= 1e-12
+    assert np.any(ref["n"][w] > x1)
+    err = np.linalg.norm(F[idx] - ref["F"], axis=1).max() / np.linalg.norm(F, axis=1).max()
+    err_w = np.linalg.norm(F[idx][w] - ref["F"][w], axis=1).max() / np.linalg.norm(F, axis=1).max()
+    print(f"  sampled normwise force error {err:.2e} (window particles {err_w:.2e})", flush=True)
+    assert err <= 1e-5
+    assert np.abs(F.sum(axis=0)).max() <= 1e-5 * np.linalg.norm(F, axis=1).max() * np.sqrt(wl.N)
+
+
 def test_sampled_melt_parity_at_full_size():
     """The full bead-spring melt (20,000 chains x 50 beads = 10^6 beads at density 0.85,
     stickers every fifth bead) at its random-walk start, in the launch configuration the

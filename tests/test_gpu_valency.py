@@ -31,3 +31,24 @@ def test_binding_raises_coordination_towards_valency():
         # the size histograms hold every cluster: their sum is the mean number of clusters
         assert np.sum(r["rho_s_all"]) * V == pytest.approx(r["clusters_per_particle"] * 4000, rel=1e-9)
         assert 0.0 <= r["P_inf"] <= 1.0 and 0.0 <= r["x_cyc"] <= 1.0
+
+
+def test_counter_geometries_suppress_core_penetration():
+    """Section 6.2 (Fig. 12) on a short run: at a deep well (E_a = 5) the uncorrected soft core
+    collapses with many particles inside each other's core, while the standard, partial and
+    blind counting shells all keep core penetrations near zero; at a shallow well (E_a = 0.5)
+    nothing collapses.  The standard shell also keeps the contacts within r_a far below the
+    uncorrected system's."""
+    from paper_2609_07842_amd import valency
+    res = valency.stability_sweep(E_as=(0.5, 5.0), steps=40_000, sample_every=1000)["results"]
+    for g, r in res.items():
+        print(f"[stability] {g}: " + ", ".join(f"E_a={e}: z {v['contacts']:.3f} pen {v['penetrations']:.4f}"
+                                               for e, v in r.items()), flush=True)
+    none5 = res["none"]["5"]["penetrations"]
+    assert none5 > 1.0
+    for g in ("standard", "partial", "blind"):
+        assert res[g]["5"]["penetrations"] < 0.05
+        assert res[g]["5"]["penetrations"] < none5 / 20
+    for g in res:
+        assert res[g]["0.5"]["penetrations"] < 0.05
+    assert res["standard"]["5"]["contacts"] < res["none"]["5"]["contacts"] / 2
