@@ -27,15 +27,17 @@ class Pair(C.Structure):
     _fields_ = [(k, C.c_double) for k in PAIR_FIELDS]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, out: str | None = None, extra_flags=()) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP), into `out` (default:
+    next to the source) with optional extra flags (the sanitizer build of the tests)."""
+    dst = out or _LIB
+    if force or not os.path.exists(dst) or os.path.getmtime(dst) < os.path.getmtime(_SRC):
+        tmp = dst + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               *extra_flags, "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, dst)
+    return dst
 
 
 _lib = None
@@ -44,9 +46,13 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        # VBC_ORACLE_LIBRARY: an already built copy (the tests' sanitizer build) instead
+        path = os.environ.get("VBC_ORACLE_LIBRARY")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         i64p = C.POINTER(C.c_int64)
         i32p = C.POINTER(C.c_int32)

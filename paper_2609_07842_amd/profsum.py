@@ -33,7 +33,7 @@ KERNEL_SRC = os.path.join(HERE, "csrc", "vbc_kernels.hip")
 # short names of the kernels of a time step (template arguments stripped)
 SHORT = {"k_force": "force", "k_count": "count", "k_embed": "embed", "k_nlist": "nlist",
          "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
-         "k_reduce": "reduce", "k_thermo": "thermo"}
+         "k_reduce": "reduce", "k_thermo_acc": "thermo"}
 BUILD_KERNELS = ("nlist", "resort")
 COPY_BYTES = 512 * 2**20
 
