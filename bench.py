@@ -238,10 +238,13 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0, re
     from paper_2609_07842_amd import tune
     wl = W.headline(f=f, seed=seed)
     # brick edge and workgroup size from the autotuner's cache when it has this workload
-    layout = tune.lookup(tune.fluid_key(wl.N, 0.5, "fp32")) or {}
+    key = tune.fluid_key(wl.N, 0.5, "fp32")
+    layout = tune.lookup(key) or {}
+    why = tune.stale(key)
     if rho_max:
         layout = dict(layout, rho_max=rho_max)
-    print(f"[bench] device {tune._device_name()}: tuned layout {layout or 'none (automatic)'}",
+    print(f"[bench] device {tune._device_name()}: tuned layout "
+          f"{layout or 'none (automatic)'}{'' if why is None else ' (tuned cache not used: ' + why + ')'}",
           file=sys.stderr, flush=True)
     s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32", **layout)
     s.set_state(wl.x, wl.v)

@@ -1318,40 +1318,22 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
 // pass 2a: dU/dn for particles inside a switching window
 // ---------------------------------------------------------------------------
 
-// Bricks per workgroup of the dU/dn pass: one wave each.
+// Waves per workgroup of the dU/dn pass; one workgroup per brick.
 constexpr int EMBED_WAVES = 4;
 
-// Like resolve_brick, for workgroups that take `per` consecutive bricks, one per wave w:
-// units of `per` bricks are dealt to the XCDs in contiguous runs.
-__device__ __forceinline__ bool brick_of_wave(const Launch &P, const Buffers &B, int per, int w, int &b)
-{
-    const int g = blockIdx.x, j = g >> 3;
-    const int T = P.list < 0 ? P.nb_launch : B.wl_n[P.list];
-    const int U = (T + per - 1) / per;
-    const int chunk = (U + 7) >> 3;
-    const int k = (g & 7) * chunk + j;
-    if (j >= chunk || k >= U) return false;
-    const int kb = k * per + w;
-    if (kb >= T) return false;
-    b = P.list < 0 ? P.b_lo + kb : B.wl[P.list][kb];
-    return true;
-}
-
-// One wave per brick over the particles that the count pass listed as inside a switching
-// window (most bricks hold a handful or none); no workgroup-wide synchronisation.
-// dU/dn of the window particles of brick b (one wave; see k_embed).  t_first: the first
-// particle of this lane's group if already read, else -1.
+// dU/dn of the window particles of brick b that fall to group g of ng groups of LPP lanes
+// (particles g, g + ng, ...; see k_embed).  t_first: the first particle of this lane's
+// group if already read, else -1.
 template <int LPP, class Real, bool MULTI>
 __device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, const RepDev &R,
                                             const PairR<Real> *pt, int b, int64_t base, int nw,
-                                            int lane, int t_first, int cur)
+                                            int lane, int g, int ng, int t_first, int cur)
 {
     // LPP lanes per window particle, EP entries of each list chunk per lane; neighbours are
     // gathered from global memory through the brick's staging map
     using R2 = typename V2<Real>::t;
     constexpr int EP = CHUNK / LPP;
     const int64_t S_ = P.nslots;
-    const int g = lane / LPP, ng = VBC_WAVE / LPP;
     R2 *sA = (R2 *)B.sA;
     const double *X = B.x[cur];
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
@@ -1452,13 +1434,16 @@ __device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, c
     }
 }
 
+// One workgroup of EMBED_WAVES waves per brick over the particles that the count pass
+// listed as inside a switching window; most bricks hold a handful or none, and then only
+// the first wave works.  No workgroup-wide synchronisation.
 template <class Real, bool MULTI>
 __global__ void k_embed(Buffers B, Launch P, int cur)
 {
     __shared__ PairR<Real> ptab[EMBED_WAVES][MAXT * MAXT];
     const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
     int b;
-    if (!brick_of_wave(P, B, EMBED_WAVES, wv, b)) return;
+    if (!brick_of_block(P, B, b)) return;
     // the brick's owner, window count and staged count read together, then the replica
     // descriptor and the first window entry before the tests (valid memory either way), so
     // that the chain of dependent reads stays short
@@ -1468,10 +1453,14 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     if (r < 0) return;
     const RepDev &R = B.reps[r];
     const int lb = b - R.b_off;
-    const int64_t S_ = P.nslots;
     const int64_t base = R.p_off + (int64_t)lb * R.bcap;
     const int t_first = B.wlst[base + lane / CHUNK];  // for eight lanes per particle
     if (nw == 0 || tot > P.stage_cap) return;  // nothing in a window, or an overflowed brick
+    // eight lanes per particle when the first wave takes all of the brick's window particles
+    // at once; with more of them, four lanes each over every wave of the workgroup, so that
+    // up to EMBED_WAVES x 16 are in flight
+    const bool one = nw <= VBC_WAVE / CHUNK;
+    if (one && wv > 0) return;
     PairR<Real> *pt = ptab[wv];
     if (MULTI) {
         const int nt = R.ntypes;
@@ -1483,10 +1472,14 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // eight lanes per particle when a wave takes all of the brick's window particles at once;
-    // with more of them, four lanes each, so that twice as many are in flight
-    if (nw <= VBC_WAVE / CHUNK) embed_brick<CHUNK, Real, MULTI>(B, P, R, pt, b, base, nw, lane, t_first, cur);
-    else embed_brick<4, Real, MULTI>(B, P, R, pt, b, base, nw, lane, -1, cur);
+    if (one) {
+        embed_brick<CHUNK, Real, MULTI>(B, P, R, pt, b, base, nw, lane, lane / CHUNK, VBC_WAVE / CHUNK,
+                                        t_first, cur);
+    } else {
+        constexpr int G = VBC_WAVE / 4;  // groups of four lanes per wave
+        embed_brick<4, Real, MULTI>(B, P, R, pt, b, base, nw, lane, wv * G + lane / 4, EMBED_WAVES * G,
+                                    -1, cur);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1580,7 +1573,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     const int64_t o_off = R.o_off;
     const uint64_t step = B.step[r];
     const uint64_t key = st.seed + R.seed;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // e, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
+    // e, -, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz; the scalar virial W is the trace, formed per brick
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool bad = false, mv = false;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
@@ -1589,7 +1583,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         int ti = MULTI ? (int)pi.w : 0;
         const Real cai = p0.c_a * sai.x;
         Real fx = 0, fy = 0, fz = 0, ei = 0;
-        Real w0 = 0, wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
+        Real wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             int ex = 0;  // pair excluded from counting and attraction (chain neighbours)
             if (MULTI && xr) {
@@ -1650,7 +1644,6 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
             fz -= phr * dz;
             if (THERMO) {
                 ei += ep;
-                w0 -= phr * r2;
                 wxx -= phr * dx * dx;
                 wyy -= phr * dy * dy;
                 wzz -= phr * dz * dz;
@@ -1694,7 +1687,6 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         if (THERMO) {
             double e_i = 0.5 * (double)ei + eb;
             acc[0] += e_i;
-            acc[1] += 0.5 * (double)w0 + wb[0];
             acc[2] += 0.5 * (double)wxx + wb[1];
             acc[3] += 0.5 * (double)wyy + wb[2];
             acc[4] += 0.5 * (double)wzz + wb[3];
@@ -1740,7 +1732,12 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     if (THERMO && threadIdx.x < 8) {
         int nw = blockDim.x / VBC_WAVE;
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+        if (threadIdx.x == 1) {
+            // W = W_xx + W_yy + W_zz, summed per wave in the same fixed order
+            for (int w = 0; w < nw; ++w) s += (red[2][w] + red[3][w]) + red[4][w];
+        } else {
+            for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+        }
         B.part[(size_t)b * 8 + threadIdx.x] = s;
     }
 }
@@ -2600,7 +2597,7 @@ hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_ou
 
 hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t s)
 {
-    unsigned g = brick_grid((P.nb_launch + EMBED_WAVES - 1) / EMBED_WAVES);
+    unsigned g = brick_grid(P.nb_launch);
     bool multi = P.multi != 0;
     const int bs = EMBED_WAVES * VBC_WAVE;
     size_t lds = 0;

@@ -2,11 +2,13 @@
 sums: the brick edge (cells per edge of the block of cells one workgroup owns, which sets
 the LDS tile and the halo overhead) and the workgroup size of the brick kernels.
 
-For a workload it times every candidate on the GPU (short warm-up, then whole steps
+For a workload it times every candidate on the GPU (the start relaxed first, the step
+graphs captured before the clock starts, then the median of three runs of whole steps
 through the captured-graph path), discards candidates that do not fit the device's LDS
 or overflow a capacity, and keeps the fastest in a JSON cache keyed by device name and
-workload.  `lookup` returns the cached choice (or None); `tune_fluid` and `tune_pool`
-fill the cache.
+workload.  Each entry records the sha256 of the kernel source it was timed with;
+`lookup` returns the cached choice only while that source is unchanged (else None, and
+`stale` says why); `tune_fluid` and `tune_pool` fill the cache.
 
     python -m paper_2609_07842_amd.tune --N 1000000 --rho 0.5 --f 4 [--precision fp32]
     python -m paper_2609_07842_amd.tune --pool
@@ -14,14 +16,23 @@ fill the cache.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import time
 
 from . import vbc as _vbc
 from . import workloads as W
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "vbc_kernels.hip")
+
+
+def kernel_hash():
+    """sha256 of the kernel source the library is built from."""
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
 BRICKS = (2, 3, 4, 5)
 BLOCKS = (128, 192, 256, 320, 384, 448, 512, 640, 768)
 
@@ -57,13 +68,26 @@ def save_cache(cache, path=CACHE):
     os.replace(tmp, path)
 
 
-def lookup(key, path=CACHE):
-    """Cached {brick, block} for a key, or None."""
+def stale(key, path=CACHE):
+    """Why the cached entry for key is not used (None if it is)."""
     e = load_cache(path).get(key)
-    return None if e is None else dict(brick=e["brick"], block=e["block"])
+    if e is None:
+        return "no entry"
+    if e.get("kernel_sha256") != kernel_hash():
+        return "timed with another kernel source"
+    return None
 
 
-def _time_fluid(wl, precision, brick, block, warmup, steps, skin):
+def lookup(key, path=CACHE):
+    """Cached {brick, block} for a key, or None if there is none or it was timed with
+    another kernel source."""
+    e = load_cache(path).get(key)
+    if e is None or e.get("kernel_sha256") != kernel_hash():
+        return None
+    return dict(brick=e["brick"], block=e["block"])
+
+
+def _time_fluid(wl, precision, brick, block, warmup, steps, skin, repeats=3):
     import torch
     s = _vbc.System(_vbc.replica(wl.N, wl.L, wl.params, skin=skin), precision=precision,
                     brick=brick, block=block)
@@ -71,18 +95,21 @@ def _time_fluid(wl, precision, brick, block, warmup, steps, skin):
     integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=1)
     s.step(warmup, **integ)
     s.check()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps, **integ)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    rates = []
+    for _ in range(repeats):
+        s.prepare_step(steps, **integ)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, **integ)
+        torch.cuda.synchronize()
+        rates.append(steps / (time.perf_counter() - t0))
     s.check()
     opts = s.options()
     s.close()
-    return steps / dt, opts
+    return statistics.median(rates), opts
 
 
-def tune_fluid(N=1_000_000, rho=0.5, f=4.0, precision="fp32", warmup=400, steps=400,
+def tune_fluid(N=1_000_000, rho=0.5, f=4.0, precision="fp32", warmup=1500, steps=400,
                skin=W.SKIN, bricks=BRICKS, blocks=BLOCKS, path=CACHE, log=print):
     """Time every (brick, block) on one fluid replica; cache and return the fastest."""
     wl = W.fluid(N, rho, f, seed=11, precision=precision)
@@ -102,7 +129,7 @@ def tune_fluid(N=1_000_000, rho=0.5, f=4.0, precision="fp32", warmup=400, steps=
     best = max(results, key=lambda r: r["steps_per_s"])
     cache = load_cache(path)
     cache[fluid_key(N, rho, precision)] = dict(best, workload=dict(N=N, rho=rho, f=f, skin=skin),
-                                               candidates=results)
+                                               candidates=results, kernel_sha256=kernel_hash())
     save_cache(cache, path)
     return best
 
@@ -132,7 +159,7 @@ def tune_pool(cfg=None, n_requests=48, steps=200, blocks=BLOCKS, bricks=(3, 4, 5
         raise RuntimeError("no candidate layout fits")
     best = max(results, key=lambda r: r["particle_steps_per_s"])
     cache = load_cache(path)
-    cache[pool_key(cfg)] = dict(best, candidates=results)
+    cache[pool_key(cfg)] = dict(best, candidates=results, kernel_sha256=kernel_hash())
     save_cache(cache, path)
     return best
 

@@ -7,10 +7,20 @@ from paper_2609_07842_amd import tune
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "t.json")
     assert tune.lookup("x", path) is None
-    tune.save_cache({"x": {"brick": 3, "block": 256, "steps_per_s": 1.0}}, path)
+    tune.save_cache({"x": {"brick": 3, "block": 256, "steps_per_s": 1.0,
+                           "kernel_sha256": tune.kernel_hash()}}, path)
     assert tune.lookup("x", path) == {"brick": 3, "block": 256}
+    assert tune.stale("x", path) is None
     with open(path) as fh:
         assert json.load(fh)["x"]["steps_per_s"] == 1.0
+
+
+def test_entries_timed_with_other_kernels_are_ignored(tmp_path):
+    path = str(tmp_path / "t.json")
+    tune.save_cache({"x": {"brick": 3, "block": 256, "kernel_sha256": "0" * 64},
+                     "y": {"brick": 4, "block": 512}}, path)
+    assert tune.lookup("x", path) is None and tune.lookup("y", path) is None
+    assert tune.stale("x", path) == "timed with another kernel source"
 
 
 def test_keys_name_device_and_workload():
