@@ -18,6 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvbc.so")
 SOURCES = ["vbc_kernels.hip", "vbc_api.hip"]
 ARCH = os.environ.get("VBC_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 
 def hipcc() -> str:
@@ -49,7 +50,8 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

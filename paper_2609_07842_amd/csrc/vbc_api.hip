@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "arena.h"
 #include "vbc_internal.h"
 
@@ -118,6 +120,15 @@ static hipError_t timed(vbc_handle h, int kind, hipStream_t s, Fn &&fn)
 }
 
 namespace {
+
+// A roctx range around an entry point: rocprofv3 --marker-trace shows the library's calls
+// beside its kernels; without a profiler attached the calls return at once.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 thread_local std::string g_err;
 
@@ -975,6 +986,7 @@ vbc_status vbc_replica_footprint(const vbc_replica_desc *d, const vbc_options *o
 vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x, const double *d_v,
                      const int32_t *d_type, uint64_t step0, hipStream_t s, int32_t *rep_out)
 {
+    Range range_("vbc_admit");
     if (!h || !d || !d_x || !rep_out) return fail(VBC_ERR_ARG, "NULL argument");
     *rep_out = -1;
     RepPlan rp;
@@ -1009,6 +1021,7 @@ vbc_status vbc_admit(vbc_handle h, const vbc_replica_desc *d, const double *d_x,
 
 vbc_status vbc_retire(vbc_handle h, int32_t rep, hipStream_t s)
 {
+    Range range_("vbc_retire");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     if (rep < 0 || rep >= h->P.nrep || !h->live[rep]) return hfail(h, VBC_ERR_ARG, "no such live replica");
     RepDev &R = h->reps[rep];
@@ -1081,6 +1094,7 @@ vbc_status vbc_tune_set(vbc_handle h, const vbc_options *t)
 vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const double *d_v,
                          const int32_t *d_type, uint64_t step0, hipStream_t s)
 {
+    Range range_("vbc_set_state");
     if (!h || !d_x) return fail(VBC_ERR_ARG, "NULL argument");
     if (rep >= h->P.nrep || (rep >= 0 && !h->live[rep])) return hfail(h, VBC_ERR_ARG, "no such live replica");
     for (int r = 0; r < h->P.nrep; ++r) {
@@ -1098,6 +1112,7 @@ vbc_status vbc_set_state(vbc_handle h, int32_t rep, const double *d_x, const dou
 
 vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hipStream_t s)
 {
+    Range range_("vbc_get_state");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     if (rep >= h->P.nrep || (rep >= 0 && !h->live[rep])) return hfail(h, VBC_ERR_ARG, "no such live replica");
     if (rep >= 0 ? !h->has_state[rep] : !all_have_state(h)) return hfail(h, VBC_ERR_STATE, "no state set");
@@ -1114,6 +1129,7 @@ vbc_status vbc_get_state(vbc_handle h, int32_t rep, double *d_x, double *d_v, hi
 
 vbc_status vbc_build_nlist(vbc_handle h, hipStream_t s)
 {
+    Range range_("vbc_build_nlist");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     VBC_NEED_STATE(h);
     bool full = false;
@@ -1129,6 +1145,7 @@ vbc_status vbc_build_nlist(vbc_handle h, hipStream_t s)
 
 vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
 {
+    Range range_("vbc_count");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
@@ -1139,6 +1156,7 @@ vbc_status vbc_count(vbc_handle h, double *d_n, hipStream_t s)
 
 vbc_status vbc_force(vbc_handle h, double *d_F, double *d_e, double *d_UW, hipStream_t s)
 {
+    Range range_("vbc_force");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
@@ -1177,6 +1195,7 @@ static StepArgs step_args(const vbc_integrator *it)
 
 vbc_status vbc_step_prepare(vbc_handle h, int32_t nsteps, const vbc_integrator *it)
 {
+    Range range_("vbc_step_prepare");
     if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
     vbc_status r = check_integrator(h, nsteps, it);
     if (r != VBC_OK) return r;
@@ -1190,6 +1209,7 @@ vbc_status vbc_step_prepare(vbc_handle h, int32_t nsteps, const vbc_integrator *
 
 vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipStream_t s)
 {
+    Range range_("vbc_step");
     if (!h || !it) return fail(VBC_ERR_ARG, "NULL argument");
     VBC_NEED_STATE(h);
     {
@@ -1233,6 +1253,7 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
 
 vbc_status vbc_check(vbc_handle h, hipStream_t s, uint32_t *flags_per_replica)
 {
+    Range range_("vbc_check");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     VBC_TRY(h, hipStreamSynchronize(s), "sync");
     std::vector<uint32_t> f(h->P.nrep);
@@ -1281,6 +1302,7 @@ vbc_status vbc_get_nlist(vbc_handle h, int32_t rep, int32_t *d_pairs, int64_t ca
 
 vbc_status vbc_observables(vbc_handle h, int32_t *d_z, int32_t *d_pen, int64_t *d_sums, hipStream_t s)
 {
+    Range range_("vbc_observables");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     VBC_NEED_STATE(h);
     VBC_LAYOUT(h, s);
@@ -1301,6 +1323,7 @@ vbc_status vbc_cluster_scratch_size(vbc_handle h, size_t *bytes)
 vbc_status vbc_clusters(vbc_handle h, void *d_scratch, size_t scratch_bytes, int32_t *d_label,
                         int64_t *d_stats, int64_t *d_hist, int32_t hist_len, hipStream_t s)
 {
+    Range range_("vbc_clusters");
     if (!h || !d_scratch) return fail(VBC_ERR_ARG, "NULL argument");
     if (scratch_bytes < 5 * cluster_array_bytes(h->P))
         return hfail(h, VBC_ERR_ARG, "scratch too small: vbc_cluster_scratch_size gives the size");
@@ -1357,6 +1380,7 @@ hipError_t scratch_address(void **out)
 vbc_status vbc_clusters_noalloc(vbc_handle h, int32_t *d_label, int64_t *d_stats, int64_t *d_hist,
                                 int32_t hist_len, hipStream_t s)
 {
+    Range range_("vbc_clusters_noalloc");
     if (!h) return fail(VBC_ERR_ARG, "NULL handle");
     const size_t need = 5 * cluster_array_bytes(h->P);
     if (need > (size_t)VBC_CLUSTERS_NOALLOC_BYTES)
@@ -1384,6 +1408,7 @@ vbc_status vbc_bond_track_size(vbc_handle h, int32_t max_partners, size_t *bytes
 vbc_status vbc_bond_track(vbc_handle h, void *d_state, size_t state_bytes, int32_t max_partners, int32_t reset,
                           int64_t *d_hist, int32_t hist_len, int64_t bin_steps, int64_t *d_stats, hipStream_t s)
 {
+    Range range_("vbc_bond_track");
     if (!h || !d_state) return fail(VBC_ERR_ARG, "NULL argument");
     size_t need = 0;
     vbc_status st = vbc_bond_track_size(h, max_partners, &need);

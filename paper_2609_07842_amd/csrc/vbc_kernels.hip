@@ -804,7 +804,13 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
 // cells of a stencil row along x are then one contiguous range, and a lane walks 9 ranges
 // instead of 27 cells (a wave pays the longest range among its lanes, about 20 % fewer
 // iterations).  Entries are the staging-order indices, so the lists are the same.
-__global__ void k_nlist(Buffers B, Launch P, int cur)
+#ifndef NLIST_ATTR
+#define NLIST_ATTR __attribute__((amdgpu_waves_per_eu(6)))
+#endif
+#ifndef SCAN_UNROLL
+#define SCAN_UNROLL 4  // candidate positions read ahead in the list build's scan
+#endif
+__global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
@@ -920,53 +926,80 @@ __global__ void k_nlist(Buffers B, Launch P, int cur)
         uint4 *wp = B.nl + i;  // where the open chunk goes
         for (int dz = 0; dz < 3; ++dz)
             for (int dy = 0; dy < 3; ++dy) {
-                // the row of three cells along x, one contiguous grid-order range
+                // the row of three cells along x, one contiguous grid-order range, in segments
+                // of 32 candidates: a tight loop marks the candidates that the FP32 pre-filter
+                // keeps, then a second loop visits only the marked ones in order, repeats the
+                // FP32 test (the few close calls to the list radius are decided in FP64) and
+                // appends.  The wave then pays the longest segment among its lanes only for
+                // the few instructions of the test, and the append only per neighbour.
                 const int q0 = lx + S.H[0] * ((ly + dy) + S.H[1] * (lz + dz));
                 const int ub = hq[q0], u1 = hq[q0 + 1], u2 = hq[q0 + 2], ue = hq[q0 + 3];
-                for (int u = ub; u < ue; ++u) {
-                    float4 pu = hpos[u];
-                    float ex = pi.x - pu.x, ey = pi.y - pu.y, ez = pi.z - pu.z;
-                    float r2f = ex * ex + ey * ey + ez * ez;
-                    if (u == hs || !(r2f < hi2)) continue;
-                    bool in = r2f < lo2;
-                    if (!in) {
-                        // near the list radius: decide with the exact FP64 expression
-                        const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
-                        const int w = T.q_w[q];
-                        int64_t js = T.q_src[q] + (u - hq[q]);
-                        double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
-                               kz = (double)unpack_w(w, 2);
-                        double r2;
-                        {
-#pragma clang fp contract(off)
-                            double tx = B.xs[i] - B.xs[js];
-                            double ty = B.xs[S_ + i] - B.xs[S_ + js];
-                            double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
-                            double ddx = tx - R.L[0] * kx;
-                            double ddy = ty - R.L[1] * ky;
-                            double ddz = tz - R.L[2] * kz;
-                            r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                for (int u0 = ub; u0 < ue; u0 += 32) {
+                    const int n = min(32, ue - u0);
+                    // bit k: candidate u0 + k lies inside the list radius, or too close to it
+                    // for FP32 to decide; SCAN_UNROLL positions are read before any is used, and
+                    // reads past the row repeat its last candidate (valid LDS) and are masked
+                    uint32_t near = 0u;
+                    for (int k0 = 0; k0 < n; k0 += SCAN_UNROLL) {
+                        float4 pu[SCAN_UNROLL];
+#pragma unroll
+                        for (int j = 0; j < SCAN_UNROLL; ++j) pu[j] = hpos[min(u0 + k0 + j, ue - 1)];
+#pragma unroll
+                        for (int j = 0; j < SCAN_UNROLL; ++j) {
+                            const float ex = pi.x - pu[j].x, ey = pi.y - pu[j].y, ez = pi.z - pu[j].z;
+                            const float r2f = ex * ex + ey * ey + ez * ez;
+                            near |= (r2f < hi2 ? 1u : 0u) << (k0 + j);
                         }
-                        in = r2 < rl2;
                     }
-                    if (in) {
-                        uint32_t hv = (uint32_t)conv[u];
-                        if (xspan > 0) {
-                            // chain neighbours up to excl_span beads apart: bit 15
+                    near &= n == 32 ? ~0u : ((1u << n) - 1u);
+                    if (u0 <= hs && hs < u0 + n) near &= ~(1u << (hs - u0));  // not the particle itself
+                    uint32_t todo = near;
+                    while (todo) {
+                        const int k = __builtin_ctz(todo);
+                        todo &= todo - 1u;
+                        const int u = u0 + k;
+                        const float4 pu = hpos[u];
+                        const float ex = pi.x - pu.x, ey = pi.y - pu.y, ez = pi.z - pu.z;
+                        bool in = ex * ex + ey * ey + ez * ez < lo2;
+                        if (!in) {
+                            // near the list radius: decide with the exact FP64 expression
                             const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
-                            const int tb = B.tags[T.q_src[q] + (u - hq[q])];
-                            const int db = ta - tb;
-                            if (ta / cl == tb / cl && db <= xspan && -db <= xspan) hv |= 0x8000u;
+                            const int w = T.q_w[q];
+                            int64_t js = T.q_src[q] + (u - hq[q]);
+                            double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
+                                   kz = (double)unpack_w(w, 2);
+                            double r2;
+                            {
+#pragma clang fp contract(off)
+                                double tx = B.xs[i] - B.xs[js];
+                                double ty = B.xs[S_ + i] - B.xs[S_ + js];
+                                double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
+                                double ddx = tx - R.L[0] * kx;
+                                double ddy = ty - R.L[1] * ky;
+                                double ddz = tz - R.L[2] * kz;
+                                r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                            }
+                            in = r2 < rl2;
                         }
-                        b3 = __builtin_amdgcn_alignbit(b3, b2, 16);
-                        b2 = __builtin_amdgcn_alignbit(b2, b1, 16);
-                        b1 = __builtin_amdgcn_alignbit(b1, b0, 16);
-                        b0 = (b0 << 16) | hv;
-                        ++nn;
-                        if (++e == CHUNK) {
-                            if (nn <= kmax) *wp = make_uint4(b0, b1, b2, b3);
-                            wp += S_;
-                            e = 0;
+                        if (in) {
+                            uint32_t hv = (uint32_t)conv[u];
+                            if (xspan > 0) {
+                                // chain neighbours up to excl_span beads apart: bit 15
+                                const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
+                                const int tb = B.tags[T.q_src[q] + (u - hq[q])];
+                                const int db = ta - tb;
+                                if (ta / cl == tb / cl && db <= xspan && -db <= xspan) hv |= 0x8000u;
+                            }
+                            b3 = __builtin_amdgcn_alignbit(b3, b2, 16);
+                            b2 = __builtin_amdgcn_alignbit(b2, b1, 16);
+                            b1 = __builtin_amdgcn_alignbit(b1, b0, 16);
+                            b0 = (b0 << 16) | hv;
+                            ++nn;
+                            if (++e == CHUNK) {
+                                if (nn <= kmax) *wp = make_uint4(b0, b1, b2, b3);
+                                wp += S_;
+                                e = 0;
+                            }
                         }
                     }
                 }

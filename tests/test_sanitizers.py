@@ -83,7 +83,8 @@ def test_c_abi_host_side_under_sanitizers(tmp_path):
     lib = str(tmp_path / "libvbc_san.so")
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
                            "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan",
-                           "-o", lib, *objs], stderr=subprocess.DEVNULL)
+                           "-o", lib, *objs, "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                           "-Wl,-rpath,/opt/rocm/lib"], stderr=subprocess.DEVNULL)
     _child([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
             os.path.join(ROOT, "tests", "test_abi.py"), os.path.join(ROOT, "tests", "test_serve_host.py"),
             os.path.join(ROOT, "tests", "test_tune_host.py")],
