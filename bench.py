@@ -535,9 +535,15 @@ def main():
             ts = Ks / r["elapsed"]
             sweep[str(f)] = {"timesteps_per_s": ts, "pair_evals_per_s": ts * r["pair_evals_per_step"],
                              "builds": r["builds"], "steps_per_rebuild": Ks / max(r["builds"], 1),
-                             "list_entries_per_particle": r["kbar"]}
-        vals = [v["timesteps_per_s"] for k, v in sweep.items() if isinstance(v, dict) and "timesteps_per_s" in v]
+                             "list_entries_per_particle": r["kbar"],
+                             # step time per list entry: separates the longer lists of a
+                             # condensing fluid from the cost of the kernels themselves
+                             "ps_per_list_entry": 1e12 / ts / (r["wl"].N * r["kbar"])}
+        rows = [v for k, v in sweep.items() if isinstance(v, dict) and "timesteps_per_s" in v]
+        vals = [v["timesteps_per_s"] for v in rows]
         sweep["flatness_max_over_min"] = max(vals) / min(vals) if vals else None
+        per = [v["ps_per_list_entry"] for v in rows]
+        sweep["flatness_per_list_entry_max_over_min"] = max(per) / min(per) if per else None
 
     paper_table = None
     if not args.no_paper_table:

@@ -506,6 +506,9 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     h->need_full.assign(C.nrep, 0);
     h->fvalid.assign(C.nrep, 0);
     h->up_pending.assign(C.nrep, 0);
+    // a fixed single replica (not a pool): count and force take its descriptor as a kernel
+    // argument (h->reps is sized once here, so the pointer stays valid)
+    h->P.one = (!pool && C.nrep == 1) ? h->reps.data() : nullptr;
     h->a_slot.init(C.nslots);
     h->a_brick.init(C.nbrick);
     h->a_cell.init(C.ncell);

@@ -137,7 +137,14 @@ struct Launch {
     int32_t any_chains;
     int32_t multi;           // general pair path: several types or chain exclusions
     int32_t precision;
+    // host side only: the one replica of a fixed single-replica handle (not a pool), whose
+    // descriptor the count and force passes then take as a kernel argument; else null
+    const RepDev *one;
 };
+
+// The replica descriptor as a kernel argument (ONE) or nothing.
+template <bool ONE> struct OneRep { int unused; };
+template <> struct OneRep<true> { RepDev R; };
 
 // internal flag bits (beyond the public ones in vbc.h)
 enum : uint32_t {

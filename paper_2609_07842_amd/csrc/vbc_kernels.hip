@@ -1033,6 +1033,15 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
 // list sweep helper
 // ---------------------------------------------------------------------------
 
+// The descriptor of replica r: the launch's own copy for a fixed single replica, else the
+// workspace's.
+template <bool ONE>
+__device__ __forceinline__ const RepDev &rep_of(const OneRep<ONE> &R1, const Buffers &B, int r)
+{
+    if constexpr (ONE) return R1.R;
+    else return B.reps[r];
+}
+
 // Visit the list of one own particle in whole chunks of eight entries (the last chunk is
 // padded with the dummy staged slot, whose terms all vanish), with the next chunk's load
 // issued before the current one is processed.  fn(staged index) is called for every entry
@@ -1154,8 +1163,8 @@ constexpr double COUNT_MARGIN = 1e-4;
 // count term by up to about 3e-6).  One group of eight lanes per particle, one list entry
 // per lane of each 16-byte chunk; the eight partial sums are added in a fixed order.
 // Writes n (FP64), s (or n with several types) and, if asked, the caller-order count.
-template <class Real, bool MULTI>
-__device__ void recount_window(const Buffers &B, const Launch &P, const RepDev &R, int b,
+template <class Real, bool MULTI, int CP>
+__device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P, const RepDev &R, int b,
                                int64_t base, int nw, const double *__restrict__ X,
                                double *__restrict__ n_out)
 {
@@ -1175,27 +1184,48 @@ __device__ void recount_window(const Buffers &B, const Launch &P, const RepDev &
         const int ti = MULTI ? B.type[i] : 0;
         const int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
-        for (int c = 0; c < nch; ++c) {
-            const uint4 q = B.nl[(size_t)c * S_ + i];
-            const uint32_t wd = (e < 2) ? q.x : (e < 4) ? q.y : (e < 6) ? q.z : q.w;
-            int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
-            int ex = 0;
-            if (MULTI && xr) {
-                ex = u >> 15;
-                u &= 0x7fff;
+        // CP chunks at a time in phases (list words, staging map, positions, terms) with no
+        // branch between the loads, so that their gathers go out together; rows past the list
+        // (every slot has nchunk rows) and the padding slot read valid memory and are masked
+        for (int c0 = 0; c0 < nch; c0 += CP) {
+            uint4 q[CP];
+#pragma unroll
+            for (int j = 0; j < CP; ++j) q[j] = B.nl[(size_t)min(c0 + j, P.nchunk - 1) * S_ + i];
+            int uj[CP], src[CP], w[CP];
+            bool vj[CP];
+#pragma unroll
+            for (int j = 0; j < CP; ++j) {
+                const uint32_t wd = (e < 2) ? q[j].x : (e < 4) ? q[j].y : (e < 6) ? q[j].z : q[j].w;
+                int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
+                bool ok = c0 + j < nch;
+                if (MULTI && xr) {
+                    ok = ok && !(u >> 15);  // excluded pair: not counted
+                    u &= 0x7fff;
+                }
+                vj[j] = ok && u != P.stage_cap;  // padding of the last chunk
+                uj[j] = vj[j] ? u : 0;
             }
-            if (u == P.stage_cap) continue;  // padding of the last chunk
-            const int src = sm[u], w = wm[u];
-            const double dx = xi0 - (X[src] + L0 * (double)unpack_w(w, 0));
-            const double dy = xi1 - (X[S_ + src] + L1 * (double)unpack_w(w, 1));
-            const double dz = xi2 - (X[2 * S_ + src] + L2 * (double)unpack_w(w, 2));
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            if (MULTI) {
-                const int tj = B.type[src];
-                if (ex || !((R.mask[ti] >> tj) & 1u)) continue;
-                acc += count_term64(r2, R.pair[ti * MAXT + tj]);
-            } else {
-                acc += count_term64(r2, p0);
+#pragma unroll
+            for (int j = 0; j < CP; ++j) {
+                src[j] = sm[uj[j]];
+                w[j] = wm[uj[j]];
+            }
+            double xj[CP][3];
+#pragma unroll
+            for (int j = 0; j < CP; ++j)
+                for (int a = 0; a < 3; ++a) xj[j][a] = X[a * S_ + src[j]];
+#pragma unroll
+            for (int j = 0; j < CP; ++j) {
+                const double dx = xi0 - (xj[j][0] + L0 * (double)unpack_w(w[j], 0));
+                const double dy = xi1 - (xj[j][1] + L1 * (double)unpack_w(w[j], 1));
+                const double dz = xi2 - (xj[j][2] + L2 * (double)unpack_w(w[j], 2));
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (MULTI) {
+                    const int tj = B.type[src[j]];
+                    if (vj[j] && ((R.mask[ti] >> tj) & 1u)) acc += count_term64(r2, R.pair[ti * MAXT + tj]);
+                } else {
+                    if (vj[j]) acc += count_term64(r2, p0);
+                }
             }
         }
 #pragma unroll
@@ -1210,8 +1240,8 @@ __device__ void recount_window(const Buffers &B, const Launch &P, const RepDev &
 
 // STATS: also count the ordered pairs inside the interaction cutoff (the pair-evaluation
 // statistic); the step loop samples it on one step in eight.
-template <class Real, bool MULTI, bool STATS>
-__global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance)
+template <class Real, bool MULTI, bool STATS, bool ONE>
+__global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance, OneRep<ONE> R1)
 {
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
@@ -1222,9 +1252,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     int b;
     if (!brick_of_block(P, B, b)) return;
     const MapFirst mf = map_prefetch(B, b, P.stage_cap);
-    const int r = B.brick_rep[b];
+    // one fixed replica: its descriptor comes with the launch, no owner lookup
+    const int r = ONE ? 0 : B.brick_rep[b];
     if (r < 0) return;
-    const RepDev &R = B.reps[r];
+    const RepDev &R = rep_of<ONE>(R1, B, r);
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
     R4 *spos = (R4 *)smem;
@@ -1333,7 +1364,10 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     if (sizeof(Real) == 4) {
         // the listed entries are in global memory, written by this workgroup before the barrier
         const int nwv = nwin;
-        if (nwv > 0) recount_window<Real, MULTI>(B, P, R, b, S.base, nwv, X, n_out);
+        // two chunks per phase where the descriptor comes with the launch; one (the plain
+        // chain of gathers) where it is read from the workspace, whose extra registers would
+        // otherwise cost the pass a workgroup per CU
+        if (nwv > 0) recount_window<Real, MULTI, ONE ? 2 : 1>(B, P, R, b, S.base, nwv, X, n_out);
     }
     if (threadIdx.x == 0) {
         B.wcnt[b] = nwin;
@@ -1542,9 +1576,9 @@ __device__ __forceinline__ void integrate_one(const StepArgs &st, int mode, bool
     }
 }
 
-template <class Real, bool MULTI, bool THERMO>
+template <class Real, bool MULTI, bool THERMO, bool ONE>
 __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
-                        double *__restrict__ F_out, double *__restrict__ e_out)
+                        double *__restrict__ F_out, double *__restrict__ e_out, OneRep<ONE> R1)
 {
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
@@ -1555,9 +1589,9 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     int b;
     if (!brick_of_block(P, B, b)) return;
     const MapFirst mf = map_prefetch(B, b, P.stage_cap);
-    const int r = B.brick_rep[b];
+    const int r = ONE ? 0 : B.brick_rep[b];
     if (r < 0) return;
-    const RepDev &R = B.reps[r];
+    const RepDev &R = rep_of<ONE>(R1, B, r);
     int lb = b - R.b_off;
     // staged per particle: position and, with one type, the switching factor s in .w plus
     // c_c A in a separate array (20 bytes in FP32); with several types the type in .w and
@@ -2610,8 +2644,15 @@ static void launch_count_t(const Buffers &B, const Launch &P, int cur, double *n
 {
     size_t lds = lds_bytes_count(P);
     unsigned g = brick_grid(P.nb_launch);
-    if (stats) k_count<Real, MULTI, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
-    else k_count<Real, MULTI, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance);
+    if (P.one) {
+        const OneRep<true> R1{*P.one};
+        if (stats) k_count<Real, MULTI, true, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+        else k_count<Real, MULTI, false, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+    } else {
+        const OneRep<false> R1{0};
+        if (stats) k_count<Real, MULTI, true, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+        else k_count<Real, MULTI, false, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+    }
 }
 
 hipError_t launch_count(const Buffers &B, const Launch &P, int cur, double *n_out, int advance,
@@ -2650,10 +2691,19 @@ static void launch_force_t(const Buffers &B, const Launch &P, int cur, Mode mode
 {
     size_t lds = lds_bytes_force(P);
     unsigned g = brick_grid(P.nb_launch);
-    if (thermo)
-        k_force<Real, MULTI, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out);
-    else
-        k_force<Real, MULTI, false><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out);
+    if (P.one) {
+        const OneRep<true> R1{*P.one};
+        if (thermo)
+            k_force<Real, MULTI, true, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+        else
+            k_force<Real, MULTI, false, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+    } else {
+        const OneRep<false> R1{0};
+        if (thermo)
+            k_force<Real, MULTI, true, false><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+        else
+            k_force<Real, MULTI, false, false><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+    }
 }
 
 hipError_t launch_force(const Buffers &B, const Launch &P, int cur, Mode mode, bool thermo,

@@ -34,7 +34,7 @@ def kernel_hash():
     with open(KERNEL_SRC, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 BRICKS = (2, 3, 4, 5)
-BLOCKS = (128, 192, 256, 320, 384, 448, 512, 640, 768)
+BLOCKS = (128, 192, 256, 320, 384, 448, 512, 640, 768, 896, 1024)
 
 
 def _device_name():
