@@ -33,7 +33,7 @@ KERNEL_SRC = os.path.join(HERE, "csrc", "vbc_kernels.hip")
 # short names of the kernels of a time step (template arguments stripped)
 SHORT = {"k_force": "force", "k_count": "count", "k_embed": "embed", "k_nlist": "nlist",
          "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
-         "k_reduce": "reduce", "k_thermo_acc": "thermo"}
+         "k_reduce": "reduce"}
 BUILD_KERNELS = ("nlist", "resort")
 COPY_BYTES = 512 * 2**20
 
@@ -128,19 +128,24 @@ def _per_dispatch(rows):
     return per
 
 
-def _calibration(per):
-    """Counter value of the largest copy dispatch (the profiled run ends with a 512 MiB
-    device copy, larger than any other copy it makes)."""
-    vals = [v for k, vs in per.items() if "copy" in k.lower() for v in vs]
-    return max(vals) if vals else None
+def _calibration(rows):
+    """Counter value of the last copy dispatch: the profiled run ends with a 512 MiB device
+    copy (earlier copies have other sizes, e.g. the bench's 1 GiB bandwidth probe)."""
+    last = None
+    for k, v, did in rows:
+        if "copy" in k.lower() and (last is None or did > last[0]):
+            last = (did, v)
+    return None if last is None else last[1]
 
 
 def traffic(fetch_dir: str, write_dir: str, sq_dir: str | None = None):
-    fetch = _per_dispatch(counter_rows(fetch_dir, "FETCH_SIZE"))
-    write = _per_dispatch(counter_rows(write_dir, "WRITE_SIZE"))
+    frows = counter_rows(fetch_dir, "FETCH_SIZE")
+    wrows = counter_rows(write_dir, "WRITE_SIZE")
+    fetch = _per_dispatch(frows)
+    write = _per_dispatch(wrows)
     copy_kib = COPY_BYTES / 1024
-    f_cal = _calibration(fetch)
-    w_cal = _calibration(write)
+    f_cal = _calibration(frows)
+    w_cal = _calibration(wrows)
     if not f_cal or not w_cal:
         raise SystemExit("no copy dispatch found for the calibration")
     ff, wf = copy_kib / f_cal, copy_kib / w_cal
