@@ -815,6 +815,7 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ StageHdr S;
     __shared__ unsigned long long lost_sum, ent_sum;
+    __shared__ unsigned pmax_bits;  // largest |p|^2 of the staged positions (FP32 bits)
     int b, r;
     if (!resolve_brick(P, B, b, r)) return;
     const RepDev &R = B.reps[r];
@@ -823,13 +824,14 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs T = carve_tabs(smem, nh_cap);
     float4 *hpos = (float4 *)after_tabs(smem, nh_cap);    // staged positions, grid order
-    int *hq = (int *)(hpos + P.stage_cap);                // first grid-order index of each cell
+    int *hq = (int *)(hpos + P.stage_cap + SCAN_UNROLL);  // first grid-order index of each cell
     uint16_t *conv = (uint16_t *)(hq + nh_cap + 4);      // grid order -> staging order
     const int64_t S_ = P.nslots;
 
     if (threadIdx.x == 0) {
         lost_sum = 0ull;
         ent_sum = 0ull;
+        pmax_bits = 0u;
     }
     stage_tables(R, b, lb, B.brick_rank0, B.cell_rank, B.cstart[1], B.ccnt[1], B.bcnt[1], S, T,
                  P.stage_cap);
@@ -885,8 +887,10 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
     __syncthreads();
     {
         // staging copy (as stage_copy), each particle also placed at its grid-order index
+        // with |p|^2 in the fourth component (brick-centred FP32 coordinates)
         const int gid = threadIdx.x / VBC_GROUP, gl = threadIdx.x % VBC_GROUP;
         const int ng = blockDim.x / VBC_GROUP;
+        float pm2 = 0.0f;
         for (int q = gid; q < S.nh; q += ng) {
             const int off = T.q_off[q], src0 = T.q_src[q], cnt = T.q_cnt[q], w = T.q_w[q], h0 = hq[q];
             for (int k = gl; k < cnt; k += VBC_GROUP) {
@@ -897,16 +901,34 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
                 p.x = (float)((B.xs[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
                 p.y = (float)((B.xs[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
                 p.z = (float)((B.xs[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
-                p.w = 0.0f;
+                p.w = fmaf(p.x, p.x, fmaf(p.y, p.y, p.z * p.z));
+                pm2 = fmaxf(pm2, p.w);
                 hpos[h0 + k] = p;
                 conv[h0 + k] = (uint16_t)t;
             }
         }
+#pragma unroll
+        for (int o = VBC_WAVE / 2; o > 0; o >>= 1) pm2 = fmaxf(pm2, __shfl_xor(pm2, o, VBC_WAVE));
+        if ((threadIdx.x % VBC_WAVE) == 0) atomicMax(&pmax_bits, __float_as_uint(pm2));  // pm2 >= 0
+        // the scan reads up to SCAN_UNROLL - 1 records past a row's end: far-away padding
+        if ((int)threadIdx.x < SCAN_UNROLL) hpos[S.total + threadIdx.x] = make_float4(1e18f, 1e18f, 1e18f, 3e36f);
     }
     __syncthreads();
 
     const double rl2 = R.rlist2;
     const float lo2 = (float)(rl2 * (1.0 - 2e-5) - 1e-4), hi2 = (float)(rl2 * (1.0 + 2e-5) + 1e-4);
+    // The pre-filter tests d = (|p_u|^2 - c_i) - 2 p_i.p_u < 0 with c_i = hi2 + margin - |p_i|^2:
+    // one subtraction and three fused steps per candidate.  With P2 the largest staged |p|^2
+    // and u = 2^-24, the rounded squares, the subtractions and the fused steps (whose partial
+    // sums stay below 4 P2 + hi2) err by less than 25 u (P2 + hi2) in total, and the direct
+    // form |p_i - p_u|^2 that decides the list differs from the exact local distance by at
+    // most 5 u hi2; the margin, 128 u (P2 + hi2), is four times their sum.  So every candidate
+    // that the direct form puts below hi2 is marked, and every candidate with d + delta < 0,
+    // delta = (hi2 + margin) - (lo2 - margin), has the direct form below lo2: such a "sure"
+    // candidate is in the list without another test, and the other marked ones are decided
+    // as before (direct form against lo2 and hi2, FP64 in between).
+    const float P2 = __uint_as_float(pmax_bits), marg = 0x1p-17f * (P2 + hi2);
+    const float hi2m = hi2 + marg, delta = hi2m - (lo2 - marg);
     const int kmax = P.k_max;
     // read once: the global descriptor cannot be kept in registers across the list stores
     const int xspan = R.excl_span, cl = R.chain_len;
@@ -919,7 +941,8 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
         int lx = loc % S.e[0], ly = (loc / S.e[0]) % S.e[1], lz = loc / (S.e[0] * S.e[1]);
         const int qs = (lx + 1) + S.H[0] * ((ly + 1) + S.H[1] * (lz + 1));
         const int hs = hq[qs] + (t - T.q_off[qs]);  // this particle in grid order
-        float4 pi = hpos[hs];
+        const float4 pi = hpos[hs];
+        const float mx = -2.0f * pi.x, my = -2.0f * pi.y, mz = -2.0f * pi.z, ci = hi2m - pi.w;
         int nn = 0, e = 0;
         // the open chunk as one 128-bit shift register, newest entry in the low half of b0
         uint32_t b0 = 0u, b1 = 0u, b2 = 0u, b3 = 0u;
@@ -935,54 +958,62 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
                 const int q0 = lx + S.H[0] * ((ly + dy) + S.H[1] * (lz + dz));
                 const int ub = hq[q0], u1 = hq[q0 + 1], u2 = hq[q0 + 2], ue = hq[q0 + 3];
                 for (int u0 = ub; u0 < ue; u0 += 32) {
-                    const int n = min(32, ue - u0);
-                    // bit k: candidate u0 + k lies inside the list radius, or too close to it
-                    // for FP32 to decide; SCAN_UNROLL positions are read before any is used, and
-                    // reads past the row repeat its last candidate (valid LDS) and are masked
-                    uint32_t near = 0u;
+                    const int n = min(32, ue - u0), cnt = (n + SCAN_UNROLL - 1) & ~(SCAN_UNROLL - 1);
+                    // the sign bit of each candidate's d shifted in from the right: candidate k
+                    // of the segment ends at bit cnt - 1 - k.  Reads past the row (into its
+                    // successors or the padding) are masked below
+                    uint32_t near = 0u, sure = 0u;
                     for (int k0 = 0; k0 < n; k0 += SCAN_UNROLL) {
+                        const float4 *pp = hpos + (u0 + k0);
                         float4 pu[SCAN_UNROLL];
 #pragma unroll
-                        for (int j = 0; j < SCAN_UNROLL; ++j) pu[j] = hpos[min(u0 + k0 + j, ue - 1)];
+                        for (int j = 0; j < SCAN_UNROLL; ++j) pu[j] = pp[j];
 #pragma unroll
                         for (int j = 0; j < SCAN_UNROLL; ++j) {
-                            const float ex = pi.x - pu[j].x, ey = pi.y - pu[j].y, ez = pi.z - pu[j].z;
-                            const float r2f = ex * ex + ey * ey + ez * ez;
-                            near |= (r2f < hi2 ? 1u : 0u) << (k0 + j);
+                            float d = pu[j].w - ci;
+                            d = fmaf(pu[j].x, mx, d);
+                            d = fmaf(pu[j].y, my, d);
+                            d = fmaf(pu[j].z, mz, d);
+                            near = __builtin_amdgcn_alignbit(near, __float_as_uint(d), 31);
+                            sure = __builtin_amdgcn_alignbit(sure, __float_as_uint(d + delta), 31);
                         }
                     }
-                    near &= n == 32 ? ~0u : ((1u << n) - 1u);
-                    if (u0 <= hs && hs < u0 + n) near &= ~(1u << (hs - u0));  // not the particle itself
+                    near &= ~((1u << (cnt - n)) - 1u);
+                    if (u0 <= hs && hs < u0 + n) near &= ~(1u << (cnt - 1 - (hs - u0)));  // not itself
                     uint32_t todo = near;
                     while (todo) {
-                        const int k = __builtin_ctz(todo);
-                        todo &= todo - 1u;
-                        const int u = u0 + k;
-                        const float4 pu = hpos[u];
-                        const float ex = pi.x - pu.x, ey = pi.y - pu.y, ez = pi.z - pu.z;
-                        bool in = ex * ex + ey * ey + ez * ez < lo2;
+                        const int bit = 31 - __builtin_clz(todo);
+                        todo &= ~(1u << bit);
+                        const int u = u0 + (cnt - 1 - bit);
+                        uint32_t hv = (uint32_t)conv[u];
+                        bool in = (sure >> bit) & 1u;
                         if (!in) {
-                            // near the list radius: decide with the exact FP64 expression
-                            const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
-                            const int w = T.q_w[q];
-                            int64_t js = T.q_src[q] + (u - hq[q]);
-                            double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
-                                   kz = (double)unpack_w(w, 2);
-                            double r2;
-                            {
+                            const float4 pu = hpos[u];
+                            const float ex = pi.x - pu.x, ey = pi.y - pu.y, ez = pi.z - pu.z;
+                            const float r2f = ex * ex + ey * ey + ez * ez;
+                            in = r2f < lo2;
+                            if (!in && r2f < hi2) {
+                                // near the list radius: decide with the exact FP64 expression
+                                const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
+                                const int w = T.q_w[q];
+                                int64_t js = T.q_src[q] + (u - hq[q]);
+                                double kx = (double)unpack_w(w, 0), ky = (double)unpack_w(w, 1),
+                                       kz = (double)unpack_w(w, 2);
+                                double r2;
+                                {
 #pragma clang fp contract(off)
-                                double tx = B.xs[i] - B.xs[js];
-                                double ty = B.xs[S_ + i] - B.xs[S_ + js];
-                                double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
-                                double ddx = tx - R.L[0] * kx;
-                                double ddy = ty - R.L[1] * ky;
-                                double ddz = tz - R.L[2] * kz;
-                                r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                                    double tx = B.xs[i] - B.xs[js];
+                                    double ty = B.xs[S_ + i] - B.xs[S_ + js];
+                                    double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
+                                    double ddx = tx - R.L[0] * kx;
+                                    double ddy = ty - R.L[1] * ky;
+                                    double ddz = tz - R.L[2] * kz;
+                                    r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                                }
+                                in = r2 < rl2;
                             }
-                            in = r2 < rl2;
                         }
                         if (in) {
-                            uint32_t hv = (uint32_t)conv[u];
                             if (xspan > 0) {
                                 // chain neighbours up to excl_span beads apart: bit 15
                                 const int q = q0 + (u >= u1 ? 1 : 0) + (u >= u2 ? 1 : 0);
@@ -2547,7 +2578,8 @@ size_t lds_bytes_nlist(const Launch &P)
 {
     // tables, grid-order positions (16 B), cell offsets, grid -> staging order (2 B)
     const size_t nh_cap = (size_t)((P.nh_max + 3) & ~3);
-    return tabs_bytes(P) + (size_t)P.stage_cap * 16 + (nh_cap + 4) * sizeof(int) + (size_t)P.stage_cap * 2;
+    return tabs_bytes(P) + (size_t)(P.stage_cap + SCAN_UNROLL) * 16 + (nh_cap + 4) * sizeof(int) +
+           (size_t)P.stage_cap * 2;
 }
 size_t lds_bytes_count(const Launch &P)
 {

@@ -31,9 +31,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "vbc_kernels.hip")
 
 # short names of the kernels of a time step (template arguments stripped)
-SHORT = {"k_force": "force", "k_count": "count", "k_embed": "embed", "k_nlist": "nlist",
-         "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
-         "k_reduce": "reduce"}
+# (the FP32 force pass with the energy and virial sums on is its own kernel, k_force_sums)
+SHORT = {"k_force": "force", "k_force_sums": "force_sums", "k_count": "count", "k_embed": "embed",
+         "k_nlist": "nlist", "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
+         "k_reduce": "reduce", "k_thermo_acc": "thermo"}
 BUILD_KERNELS = ("nlist", "resort")
 COPY_BYTES = 512 * 2**20
 
@@ -150,7 +151,7 @@ def traffic(fetch_dir: str, write_dir: str, sq_dir: str | None = None):
         raise SystemExit("no copy dispatch found for the calibration")
     ff, wf = copy_kib / f_cal, copy_kib / w_cal
     kernels = {}
-    for k in ("force", "count", "embed", "nlist", "resort", "kick", "thermo"):
+    for k in ("force", "force_sums", "count", "embed", "nlist", "resort", "kick", "thermo"):
         fv, wv = fetch.get(k, []), write.get(k, [])
         if not fv or not wv:
             continue
