@@ -1191,16 +1191,20 @@ constexpr double COUNT_MARGIN = 1e-4;
 // entries of wlst): their switching factor s and dU/dn depend steeply on n (eq. (Psi),
 // eq. (Psidelta)), so the count is summed again from the FP64 positions, gathered through
 // the brick's staging map, instead of the FP32 staged ones (whose rounding would move each
-// count term by up to about 3e-6).  One group of eight lanes per particle, one list entry
-// per lane of each 16-byte chunk; the eight partial sums are added in a fixed order.
-// Writes n (FP64), s (or n with several types) and, if asked, the caller-order count.
-template <class Real, bool MULTI, int CP>
+// count term by up to about 3e-6).  A group of LANES lanes per particle: lane l takes list
+// entry l % 8 of chunk l / 8 (+ LANES / 8 per further chunk it reads), CP chunks per lane
+// in a phase of three dependent gathers (list chunk, staging map, position) that go out
+// together; the partial sums are added in a fixed order.  Writes n (FP64), s (or n with
+// several types) and, if asked, the caller-order count.
+template <class Real, bool MULTI, int LANES, int CP>
 __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P, const RepDev &R, int b,
                                int64_t base, int nw, const double *__restrict__ X,
                                double *__restrict__ n_out)
 {
     using R2 = typename V2<Real>::t;
-    const int g = threadIdx.x / CHUNK, e = threadIdx.x % CHUNK, ng = blockDim.x / CHUNK;
+    constexpr int CG = LANES / CHUNK;  // chunks read side by side by one group
+    const int g = threadIdx.x / LANES, l = threadIdx.x % LANES, ng = blockDim.x / LANES;
+    const int e = l % CHUNK, cl = l / CHUNK;
     const int64_t S_ = P.nslots;
     const int32_t *sm = B.smap + (size_t)b * P.stage_cap;
     const uint8_t *wm = B.wmap + (size_t)b * P.stage_cap;
@@ -1215,20 +1219,19 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
         const int ti = MULTI ? B.type[i] : 0;
         const int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
-        // CP chunks at a time in phases (list words, staging map, positions, terms) with no
-        // branch between the loads, so that their gathers go out together; rows past the list
-        // (every slot has nchunk rows) and the padding slot read valid memory and are masked
-        for (int c0 = 0; c0 < nch; c0 += CP) {
+        // no branch between the loads of a phase; rows past the list (every slot has nchunk
+        // rows) and the padding slot read valid memory and are masked
+        for (int c0 = 0; c0 < nch; c0 += CG * CP) {
             uint4 q[CP];
 #pragma unroll
-            for (int j = 0; j < CP; ++j) q[j] = B.nl[(size_t)min(c0 + j, P.nchunk - 1) * S_ + i];
+            for (int j = 0; j < CP; ++j) q[j] = B.nl[(size_t)min(c0 + cl + j * CG, P.nchunk - 1) * S_ + i];
             int uj[CP], src[CP], w[CP];
             bool vj[CP];
 #pragma unroll
             for (int j = 0; j < CP; ++j) {
                 const uint32_t wd = (e < 2) ? q[j].x : (e < 4) ? q[j].y : (e < 6) ? q[j].z : q[j].w;
                 int u = (int)((wd >> (16 * (e & 1))) & 0xffffu);
-                bool ok = c0 + j < nch;
+                bool ok = c0 + cl + j * CG < nch;
                 if (MULTI && xr) {
                     ok = ok && !(u >> 15);  // excluded pair: not counted
                     u &= 0x7fff;
@@ -1260,8 +1263,8 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
             }
         }
 #pragma unroll
-        for (int o = CHUNK / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, CHUNK);
-        if (e == 0) {
+        for (int o = LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LANES);
+        if (l == 0) {
             B.nd[i] = acc;
             sA[i] = R2{MULTI ? (Real)acc : (Real)omega_d64(acc, p0.x1, p0.x2), Real(0)};
             if (n_out) n_out[R.o_off + B.tag[i]] = acc;
@@ -1272,7 +1275,7 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
 // STATS: also count the ordered pairs inside the interaction cutoff (the pair-evaluation
 // statistic); the step loop samples it on one step in eight.
 template <class Real, bool MULTI, bool STATS, bool ONE>
-__global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance, OneRep<ONE> R1)
+__global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out, int advance, OneRep<ONE> R1)
 {
     using R4 = typename V4<Real>::t;
     using R2 = typename V2<Real>::t;
@@ -1395,10 +1398,14 @@ __global__ void k_count(Buffers B, Launch P, int cur, double *__restrict__ n_out
     if (sizeof(Real) == 4) {
         // the listed entries are in global memory, written by this workgroup before the barrier
         const int nwv = nwin;
-        // two chunks per phase where the descriptor comes with the launch; one (the plain
-        // chain of gathers) where it is read from the workspace, whose extra registers would
-        // otherwise cost the pass a workgroup per CU
-        if (nwv > 0) recount_window<Real, MULTI, ONE ? 2 : 1>(B, P, R, b, S.base, nwv, X, n_out);
+        // few listed particles (as in a fluid off its switching windows): 32 lanes each, so a
+        // list of up to 32 entries takes one phase; many: 8 lanes each, two chunks per phase
+        // where the descriptor comes with the launch (one where it is read from the
+        // workspace, whose extra registers would cost the pass a workgroup per CU)
+        if (nwv > 0 && nwv * 32 <= (int)blockDim.x)
+            recount_window<Real, MULTI, 32, 1>(B, P, R, b, S.base, nwv, X, n_out);
+        else if (nwv > 0)
+            recount_window<Real, MULTI, CHUNK, 1>(B, P, R, b, S.base, nwv, X, n_out);
     }
     if (threadIdx.x == 0) {
         B.wcnt[b] = nwin;
