@@ -1398,12 +1398,12 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
     if (sizeof(Real) == 4) {
         // the listed entries are in global memory, written by this workgroup before the barrier
         const int nwv = nwin;
-        // few listed particles (as in a fluid off its switching windows): 32 lanes each, so a
-        // list of up to 32 entries takes one phase; many: 8 lanes each, two chunks per phase
-        // where the descriptor comes with the launch (one where it is read from the
-        // workspace, whose extra registers would cost the pass a workgroup per CU)
+        // as many lanes per listed particle (32, 16 or 8) as one round of the workgroup
+        // allows: 32 take a list of up to 32 entries in one phase, 16 in two, 8 in four
         if (nwv > 0 && nwv * 32 <= (int)blockDim.x)
             recount_window<Real, MULTI, 32, 1>(B, P, R, b, S.base, nwv, X, n_out);
+        else if (nwv > 0 && nwv * 16 <= (int)blockDim.x)
+            recount_window<Real, MULTI, 16, 1>(B, P, R, b, S.base, nwv, X, n_out);
         else if (nwv > 0)
             recount_window<Real, MULTI, CHUNK, 1>(B, P, R, b, S.base, nwv, X, n_out);
     }
