@@ -80,14 +80,16 @@ struct Buffers {
     int32_t *ccnt[2];        // [sum ncell] particles in each cell (by rank)
     int32_t *bcnt[2];        // [nbrick_tot] particles in each brick
     int32_t *bfill;          // [nbrick_tot] counters of the full (unsorted-input) build
-    double *x[2];            // positions SoA [3][nslots], double-buffered by step parity
+    double *x[2];            // positions [nslots][3] (the three coordinates of a slot side by
+                             // side, so that a cell's particles gathered into a neighbour's
+                             // halo are one contiguous run), double-buffered by step parity
     double *v;               // velocities SoA [3][nslots]
     double *Fst;             // forces kept between calls SoA [3][nslots]
     double *xref;            // positions at the last build SoA [3][nslots]
     int32_t *tag;            // [nslots]
     int32_t *type;           // [nslots]
     uint8_t *lcell;          // [nslots] cell of the particle inside its brick
-    double *xs;              // next layout: positions SoA [3][nslots]
+    double *xs;              // next layout: positions [nslots][3]
     double *vs;              // next layout: velocities
     int32_t *tags, *types;   // next layout
     uint8_t *lcells;         // next layout

@@ -412,7 +412,7 @@ __global__ void k_set_state(Buffers B, int64_t S_, int cur, int r, int64_t in_of
     int64_t i = in_off + tg;
     int64_t d = R.p_off + tg;
     for (int a = 0; a < 3; ++a) {
-        B.x[cur][a * S_ + d] = x[a * in_stride + i];
+        B.x[cur][3 * d + a] = x[a * in_stride + i];
         B.v[a * S_ + d] = v ? v[a * in_stride + i] : 0.0;
     }
     B.tag[d] = (int32_t)tg;
@@ -436,7 +436,7 @@ __global__ void k_get_state(Buffers B, int64_t S_, int cur, int r, int64_t out_o
     int64_t slot = R.p_off + k;
     int64_t dst = out_off + B.tag[slot];
     for (int a = 0; a < 3; ++a) {
-        if (x) x[a * out_stride + dst] = wrap1(B.x[cur][a * S_ + slot], R.L[a]);
+        if (x) x[a * out_stride + dst] = wrap1(B.x[cur][3 * slot + a], R.L[a]);
         if (v) v[a * out_stride + dst] = B.v[a * S_ + slot];
     }
 }
@@ -620,7 +620,7 @@ __device__ void place_members(const Buffers &B, const RepDev &R, int r, int b,
         int64_t ns = S.base + lo + rank;
         int64_t o = T.m_src[m];
         for (int a = 0; a < 3; ++a) {
-            B.xs[a * S_ + ns] = wrap1(B.x[cur][a * S_ + o], R.L[a]);
+            B.xs[3 * ns + a] = wrap1(B.x[cur][3 * o + a], R.L[a]);
             B.vs[a * S_ + ns] = B.v[a * S_ + o];
         }
         B.tags[ns] = key;
@@ -658,13 +658,13 @@ __global__ void k_gbin(Buffers B, int64_t S_, int cur, int r)
     int c[3];
     bool bad = false;
     for (int a = 0; a < 3; ++a) {
-        double t = B.x[cur][a * S_ + d];
+        double t = B.x[cur][3 * d + a];
         if (!isfinite(t)) {
             bad = true;
             t = 0.0;
         }
         t = wrap1(t, R.L[a]);
-        B.x[cur][a * S_ + d] = t;
+        B.x[cur][3 * d + a] = t;
         c[a] = cell_of(t, R.h[a], R.nc[a]) / R.bd[a];
     }
     if (bad) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_NONFINITE);
@@ -701,7 +701,7 @@ __global__ void k_gsort(Buffers B, Launch P, int cur)
     const int64_t S_ = P.nslots;
     for (int m = threadIdx.x; m < nmem; m += blockDim.x) {
         int d = B.src[S.base + m];
-        double xw[3] = {B.x[cur][d], B.x[cur][S_ + d], B.x[cur][2 * S_ + d]};
+        double xw[3] = {B.x[cur][3 * d], B.x[cur][3 * d + 1], B.x[cur][3 * d + 2]};
         int lc = local_cell(R, S, xw);
         if (lc < 0) lc = 0;  // not reached: binned from the same wrapped coordinates
         T.m_src[m] = d;
@@ -761,7 +761,7 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     const int bcap = R.bcap;
     auto member = [&](int src, bool ok) {
         double xw[3];
-        for (int a = 0; a < 3; ++a) xw[a] = wrap1(B.x[cur][a * S_ + src], R.L[a]);
+        for (int a = 0; a < 3; ++a) xw[a] = wrap1(B.x[cur][3 * src + a], R.L[a]);
         const int tg = B.tag[src];
         int lc = local_cell(R, S, xw);
         if (ok && lc >= 0) {
@@ -840,8 +840,8 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
         for (int a = 0; a < 3; ++a) {
-            double xa = B.xs[a * S_ + i];
-            B.x[cur][a * S_ + i] = xa;
+            double xa = B.xs[3 * i + a];
+            B.x[cur][3 * i + a] = xa;
             B.xref[a * S_ + i] = xa;
             B.v[a * S_ + i] = B.vs[a * S_ + i];
         }
@@ -898,9 +898,9 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
                 sm[t] = src;
                 wm[t] = (uint8_t)w;
                 float4 p;
-                p.x = (float)((B.xs[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
-                p.y = (float)((B.xs[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
-                p.z = (float)((B.xs[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
+                p.x = (float)((B.xs[3 * src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
+                p.y = (float)((B.xs[3 * src + 1] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
+                p.z = (float)((B.xs[3 * src + 2] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
                 p.w = fmaf(p.x, p.x, fmaf(p.y, p.y, p.z * p.z));
                 pm2 = fmaxf(pm2, p.w);
                 hpos[h0 + k] = p;
@@ -1002,9 +1002,9 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
                                 double r2;
                                 {
 #pragma clang fp contract(off)
-                                    double tx = B.xs[i] - B.xs[js];
-                                    double ty = B.xs[S_ + i] - B.xs[S_ + js];
-                                    double tz = B.xs[2 * S_ + i] - B.xs[2 * S_ + js];
+                                    double tx = B.xs[3 * i] - B.xs[3 * js];
+                                    double ty = B.xs[3 * i + 1] - B.xs[3 * js + 1];
+                                    double tz = B.xs[3 * i + 2] - B.xs[3 * js + 2];
                                     double ddx = tx - R.L[0] * kx;
                                     double ddy = ty - R.L[1] * ky;
                                     double ddz = tz - R.L[2] * kz;
@@ -1154,9 +1154,9 @@ __device__ __forceinline__ typename V4<Real>::t local_pos(const RepDev &R, const
                                                           int64_t S_, int src, int w, int type)
 {
     typename V4<Real>::t p;
-    p.x = (Real)((X[src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
-    p.y = (Real)((X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
-    p.z = (Real)((X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
+    p.x = (Real)((X[3 * src] + R.L[0] * (double)unpack_w(w, 0)) - S.O[0]);
+    p.y = (Real)((X[3 * src + 1] + R.L[1] * (double)unpack_w(w, 1)) - S.O[1]);
+    p.z = (Real)((X[3 * src + 2] + R.L[2] * (double)unpack_w(w, 2)) - S.O[2]);
     p.w = (Real)type;
     return p;
 }
@@ -1215,7 +1215,7 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
     for (int k = g; k < nw; k += ng) {
         const int t = B.wlst[base + k];
         const int64_t i = base + t;
-        const double xi0 = X[i], xi1 = X[S_ + i], xi2 = X[2 * S_ + i];
+        const double xi0 = X[3 * i], xi1 = X[3 * i + 1], xi2 = X[3 * i + 2];
         const int ti = MULTI ? B.type[i] : 0;
         const int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
@@ -1247,7 +1247,7 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
             double xj[CP][3];
 #pragma unroll
             for (int j = 0; j < CP; ++j)
-                for (int a = 0; a < 3; ++a) xj[j][a] = X[a * S_ + src[j]];
+                for (int a = 0; a < 3; ++a) xj[j][a] = X[3 * src[j] + a];
 #pragma unroll
             for (int j = 0; j < CP; ++j) {
                 const double dx = xi0 - (xj[j][0] + L0 * (double)unpack_w(w[j], 0));
@@ -1450,7 +1450,7 @@ __device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, c
         int64_t i = base + t;
         double n_i = B.nd[i];
         int ti = MULTI ? B.type[i] : 0;
-        const double xi0 = X[i], xi1 = X[S_ + i], xi2 = X[2 * S_ + i];
+        const double xi0 = X[3 * i], xi1 = X[3 * i + 1], xi2 = X[3 * i + 2];
         int nch = (B.nn[i] + CHUNK - 1) / CHUNK;
         double acc = 0.0;
         if (!MULTI) {
@@ -1487,7 +1487,7 @@ __device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, c
                 double xj[4][3];
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    for (int a = 0; a < 3; ++a) xj[j][a] = X[a * S_ + sj[j]];
+                    for (int a = 0; a < 3; ++a) xj[j][a] = X[3 * sj[j] + a];
                 Real sjv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) sjv[j] = sA[sj[j]].x;
@@ -1513,9 +1513,9 @@ __device__ __forceinline__ void embed_brick(const Buffers &B, const Launch &P, c
                 }
                 if (u == P.stage_cap) continue;  // padding
                 int src = sm[u], w = wm[u];
-                Real dx = (Real)(xi0 - (X[src] + R.L[0] * (double)unpack_w(w, 0)));
-                Real dy = (Real)(xi1 - (X[S_ + src] + R.L[1] * (double)unpack_w(w, 1)));
-                Real dz = (Real)(xi2 - (X[2 * S_ + src] + R.L[2] * (double)unpack_w(w, 2)));
+                Real dx = (Real)(xi0 - (X[3 * src] + R.L[0] * (double)unpack_w(w, 0)));
+                Real dy = (Real)(xi1 - (X[3 * src + 1] + R.L[1] * (double)unpack_w(w, 1)));
+                Real dz = (Real)(xi2 - (X[3 * src + 2] + R.L[2] * (double)unpack_w(w, 2)));
                 Real r2 = dx * dx + dy * dy + dz * dz;
                 int tj = B.type[src];
                 const PairR<Real> &q2 = pt[ti * MAXT + tj];
@@ -1759,7 +1759,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         });
         double F[3] = {(double)fx, (double)fy, (double)fz};
         double eb = 0.0, wb[7] = {0, 0, 0, 0, 0, 0, 0};
-        double xi_[3] = {X[i], X[S_ + i], X[2 * S_ + i]};
+        double xi_[3] = {X[3 * i], X[3 * i + 1], X[3 * i + 2]};
         int32_t tg = B.tag[i];
         if (chain_len > 1) {
             // harmonic bonds to the neighbouring beads of the same chain
@@ -1769,7 +1769,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 int64_t j = B.inv[o_off + tg + side];
                 double d[3];
                 for (int a = 0; a < 3; ++a) {
-                    double tt = xi_[a] - X[a * S_ + j];
+                    double tt = xi_[a] - X[3 * j + a];
                     d[a] = tt - R.L[a] * rint(tt / R.L[a]);
                 }
                 double rb = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
@@ -1815,7 +1815,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 double *Xn = B.x[cur ^ 1];
                 double d2 = 0.0;
                 for (int a = 0; a < 3; ++a) {
-                    Xn[a * S_ + i] = xx[a];
+                    Xn[3 * i + a] = xx[a];
                     double dd = xx[a] - B.xref[a * S_ + i];
                     d2 += dd * dd;
                 }
@@ -1865,13 +1865,13 @@ __global__ void k_kick_drift(Buffers B, Launch P, int cur, StepArgs st)
         for (int a = 0; a < 3; ++a) {
             F[a] = B.Fst[a * S_ + i];
             v[a] = B.v[a * S_ + i];
-            x[a] = B.x[cur][a * S_ + i];
+            x[a] = B.x[cur][3 * i + a];
         }
         integrate_one(st, MODE_MID, true, F, v, x, key, (uint64_t)B.tag[i], step);
         double d2 = 0.0;
         for (int a = 0; a < 3; ++a) {
             B.v[a * S_ + i] = v[a];
-            B.x[cur ^ 1][a * S_ + i] = x[a];
+            B.x[cur ^ 1][3 * i + a] = x[a];
             double dd = x[a] - B.xref[a * S_ + i];
             d2 += dd * dd;
         }
@@ -1981,7 +1981,7 @@ __device__ __forceinline__ double obs_r2(const RepDev &R, const double *__restri
     double d[3];
     for (int a = 0; a < 3; ++a) {
         const double La = R.L[a];
-        const double tt = wi[a] - wrap1(X[a * S_ + j], La);
+        const double tt = wi[a] - wrap1(X[3 * j + a], La);
         const double at = fabs(tt);
         double k;
         if (at < 0.375 * La) k = 0.0;
@@ -2024,7 +2024,7 @@ __device__ __forceinline__ bool within(float r2f, const Band &bd, const RepDev &
     if (r2f < bd.lo) return true;
     if (!(r2f < bd.hi)) return false;
     double wi[3];
-    for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[a * S_ + i], R.L[a]);
+    for (int a = 0; a < 3; ++a) wi[a] = wrap1(X[3 * i + a], R.L[a]);
     return obs_r2(R, X, S_, wi, j) < bd.c2;
 }
 
