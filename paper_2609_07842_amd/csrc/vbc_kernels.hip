@@ -728,12 +728,15 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     int b;
     if (!brick_of_block(P, B, b)) return;
     const MapFirst mf = map_prefetch(B, b, P.stage_cap);
+    // replica 0's flags read beside the owner: with one replica (the usual case) the test
+    // that ends most launches needs no dependent read
+    const uint32_t fl0 = B.flags[0];
     const int r = B.brick_rep[b];
     const int tot = B.stotal[b];
     if (r < 0) return;
-    const RepDev &R = B.reps[r];
-    uint32_t fl = B.flags[r];
+    const uint32_t fl = r == 0 ? fl0 : B.flags[r];
     if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
+    const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs Q = carve_tabs(smem, nh_cap);
@@ -817,9 +820,10 @@ __global__ void NLIST_ATTR k_nlist(Buffers B, Launch P, int cur)
     __shared__ unsigned long long lost_sum, ent_sum;
     __shared__ unsigned pmax_bits;  // largest |p|^2 of the staged positions (FP32 bits)
     int b, r;
+    const uint32_t fl0 = B.flags[0];  // as in k_resort
     if (!resolve_brick(P, B, b, r)) return;
+    if (!((r == 0 ? fl0 : B.flags[r]) & (VBC_FLAG_REBUILD | FLAG_FULL))) return;
     const RepDev &R = B.reps[r];
-    if (!(B.flags[r] & (VBC_FLAG_REBUILD | FLAG_FULL))) return;
     int lb = b - R.b_off;
     int nh_cap = (P.nh_max + 3) & ~3;
     StageTabs T = carve_tabs(smem, nh_cap);
@@ -1549,18 +1553,17 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     const int wv = threadIdx.x / VBC_WAVE, lane = threadIdx.x % VBC_WAVE;
     int b;
     if (!brick_of_block(P, B, b)) return;
-    // the brick's owner, window count and staged count read together, then the replica
-    // descriptor and the first window entry before the tests (valid memory either way), so
-    // that the chain of dependent reads stays short
+    // the brick's owner, window count and staged count read together: most bricks have no
+    // window particle and leave here; then the replica descriptor and the first window entry
     const int r = B.brick_rep[b];
     const int nw = B.wcnt[b];
     const int tot = B.stotal[b];
-    if (r < 0) return;
+    // free brick, nothing in a window, or an overflowed brick
+    if (r < 0 || nw == 0 || tot > P.stage_cap) return;
     const RepDev &R = B.reps[r];
     const int lb = b - R.b_off;
     const int64_t base = R.p_off + (int64_t)lb * R.bcap;
     const int t_first = B.wlst[base + lane / CHUNK];  // for eight lanes per particle
-    if (nw == 0 || tot > P.stage_cap) return;  // nothing in a window, or an overflowed brick
     // eight lanes per particle when the first wave takes all of the brick's window particles
     // at once; with more of them, four lanes each over every wave of the workgroup, so that
     // up to EMBED_WAVES x 16 are in flight
