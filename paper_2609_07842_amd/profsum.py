@@ -31,9 +31,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "vbc_kernels.hip")
 
 # short names of the kernels of a time step (template arguments stripped)
-# (the FP32 force pass with the energy and virial sums on is its own kernel, k_force_sums)
-SHORT = {"k_force": "force", "k_force_sums": "force_sums", "k_count": "count", "k_embed": "embed",
-         "k_nlist": "nlist", "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
+# (the force pass with the energy and virial sums on is told apart by its template
+# arguments, see short_name)
+SHORT = {"k_force": "force", "k_count": "count", "k_embed": "embed", "k_nlist": "nlist",
+         "k_resort": "resort", "k_worklist": "worklist", "k_kick_drift": "kick",
          "k_reduce": "reduce", "k_thermo_acc": "thermo"}
 BUILD_KERNELS = ("nlist", "resort")
 COPY_BYTES = 512 * 2**20
@@ -45,8 +46,13 @@ def source_sha256() -> str:
 
 
 def short_name(kernel: str) -> str:
-    base = kernel.split("(")[0].split("<")[0].strip()
-    base = base.split("::")[-1]
+    head = kernel.split("(")[0]
+    base = head.split("<")[0].strip().split("::")[-1]
+    if base == "k_force" and "<" in head:
+        # k_force<Real, MULTI, THERMO, ONE>: the pass with the energy and virial sums on
+        args = [a.strip() for a in head.split("<", 1)[1].rsplit(">", 1)[0].split(",")]
+        if len(args) > 2 and args[2] == "true":
+            return "force_sums"
     return SHORT.get(base, base)
 
 
@@ -175,6 +181,35 @@ def traffic(fetch_dir: str, write_dir: str, sq_dir: str | None = None):
             "kernels": kernels}
 
 
+def counters(dirs):
+    """Mean value per dispatch of every counter in the given --pmc runs, per kernel of a
+    time step (list-build kernels: the dispatches that built, told apart by their VALU
+    instruction count, or by the run's first counter)."""
+    out = {}
+    for d in dirs:
+        names = []
+        for r in _read_rows(d, "counter_collection.csv"):
+            n = _col(r, "Counter_Name")
+            if n not in names:
+                names.append(n)
+        per = {n: _per_dispatch(counter_rows(d, n)) for n in names}
+        key = "SQ_INSTS_VALU" if "SQ_INSTS_VALU" in per else names[0]
+        for k in ("force", "force_sums", "count", "embed", "nlist", "resort", "kick", "thermo"):
+            sel = None
+            if k in BUILD_KERNELS and per[key].get(k):
+                ref = per[key][k]
+                cut = max(ref) / 3.0
+                sel = [i for i, v in enumerate(ref) if v > cut]
+            for n in names:
+                vals = per[n].get(k, [])
+                if sel is not None:
+                    vals = [vals[i] for i in sel if i < len(vals)]
+                if vals:
+                    out.setdefault(k, {})[n] = statistics.fmean(vals)
+                    out[k].setdefault("dispatches", len(vals))
+    return out
+
+
 def _md_trace(title, cmd, summ):
     lines = [f"# Kernel trace: {title}", "", "Command:", "", f"    {cmd}", "",
              "| kernel | dispatches | mean us | median us | total ms | real builds | mean us per build |",
@@ -201,7 +236,16 @@ def main(argv=None):
     c.add_argument("--workload", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--cmd", action="append", default=[])
+    q = sub.add_parser("counters")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.what == "counters":
+        rec = {"source_sha256": source_sha256(), "kernels": counters(a.dirs)}
+        with open(a.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec["kernels"], indent=1))
+        return 0
     if a.what == "trace":
         summ = trace_summary(a.dir)
         text = _md_trace(a.title, a.cmd, summ)
