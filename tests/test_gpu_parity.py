@@ -60,7 +60,8 @@ CASES = [
     ("exchange_tuned_f2", 1500, W.box_length(1500, 0.12), W.exchange_tuned(E_a=4.0, f=2.0)),
     ("three_cells", 117, 7.3, W.vbc_params(E_a=5.0, f=2.0)),
     # counts near 10-11 at this density: many particles per brick in the switching window,
-    # so the dU/dn pass takes its LDS-staged branch
+    # so the dU/dn pass spreads them over every wave of its workgroup, and the count pass
+    # recounts them in FP64
     ("window_heavy_f10", 4000, W.box_length(4000, 0.5), W.vbc_params(E_a=5.0, f=10.0)),
 ]
 
@@ -79,6 +80,43 @@ def test_neighbour_list_bit_exact(name, N, L, params):
     # every unordered pair is listed from both ends
     assert cnt == 2 * len(gpu)
     ref = {tuple(p) for p in oracle.neighbor_pairs(x, L, _rlist(params)).tolist()}
+    assert gpu == ref
+
+
+def test_neighbour_list_near_the_list_radius():
+    # pairs placed at r_list (1 + d) for d from -1e-3 to 1e-3, down to one rounding step, in
+    # random directions, some across the periodic faces: the list build's FP32 pre-filter,
+    # its "surely inside" mask and the FP64 test near the radius must together reproduce the
+    # exact neighbour set
+    print("[nlist] near the list radius", flush=True)
+    params = W.vbc_params(E_a=5.0, f=2.0)
+    L = 14.0
+    rl = _rlist(params)
+    rng = np.random.default_rng(11)
+    deltas = [-1e-3, -1e-5, -2e-5, -1e-7, -1e-9, -1e-12, -1e-15, 0.0, 1e-15, 1e-12, 1e-9, 1e-7, 2e-5,
+              1e-5, 1e-3]
+    pts = [rng.uniform(0.0, L, size=(200, 3))]
+    for k in range(180):
+        d = deltas[k % len(deltas)]
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        c = rng.uniform(0.0, L, size=3)
+        h = 0.5 * rl * (1.0 + d) * u
+        pts.append(np.mod(np.stack([c - h, c + h]), L))
+    x = np.concatenate(pts)
+    x = np.where(x >= L, x - L, x)  # inside [0, L), as the GPU keeps them
+    N = x.shape[0]
+    s = _system(N, L, params)
+    s.set_state(x)
+    s.build_nlist()
+    pairs, cnt = s.nlist_pairs(0)
+    s.check()
+    gpu = {(min(a, b), max(a, b)) for a, b in pairs.tolist()}
+    assert cnt == 2 * len(gpu)
+    ref = {tuple(p) for p in oracle.neighbor_pairs(x, L, rl).tolist()}
+    # the placed pairs straddle the radius: both sides are present
+    placed = {(200 + 2 * k, 201 + 2 * k) for k in range(180)}
+    assert 40 < len(placed & ref) < 140
     assert gpu == ref
 
 
@@ -114,6 +152,24 @@ def test_fp32_mixed_parity(name, N, L, params):
     esc = np.abs(ref["e"]).sum()
     assert abs(UW[0, 0] - ref["U"]) <= 1e-5 * max(1.0, esc)
     assert abs(UW[0, 1] - ref["W"]) <= 1e-5 * max(1.0, np.abs(ref["W"]) + esc)
+
+
+@pytest.mark.parametrize("block", [128, 256, 1024])
+@pytest.mark.parametrize("name", ["window_rho0.1_f2", "window_heavy_f10"])
+def test_fp32_window_recount_every_lane_split(name, block):
+    # the count pass recounts the particles it lists near a switching window with 32, 16 or
+    # 8 lanes each, depending on how many a brick lists against the workgroup size: small
+    # and large workgroups over sparse and crowded windows take every split
+    _, N, L, params = next(c for c in CASES if c[0] == name)
+    print(f"[fp32 recount] {name} N={N} block={block}", flush=True)
+    x = W.uniform_positions(N, L, seed=N + 5)
+    ref = oracle.evaluate(x, L, params)
+    n, F, e, UW = _gpu_eval(_system(N, L, params, precision="fp32", block=block), x)
+    win = (ref["n"] > params["f"] - params["delta"]) & (ref["n"] < params["f"] - params["delta"] + 1)
+    assert win.sum() > 20
+    assert np.abs(n[win] - ref["n"][win]).max() <= 1e-12
+    assert np.abs(n - ref["n"]).max() <= 1e-5
+    assert _normwise(F, ref["F"]) <= 1e-5
 
 
 def test_multitype_parity_both_precisions():
