@@ -479,7 +479,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus}, WORLD_SIZE={world} requested); "
-              "this build runs each system on a single MI355X and has no multi-GPU path.",
+              "the library runs each system on a single MI355X and has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 
