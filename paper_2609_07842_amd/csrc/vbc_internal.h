@@ -94,7 +94,7 @@ struct Buffers {
     int32_t *tags, *types;   // next layout
     uint8_t *lcells;         // next layout
     int32_t *src;            // [nslots] full build: members of each brick (dense index)
-    int32_t *inv;            // [ntot] caller index (o_off + tag) -> slot
+    int32_t *inv;            // [ntot] caller index (o_off + tag) -> slot (kept for chains only)
     int32_t *smap;           // [nbrick_tot][stage_cap] source slot of each staged particle
     uint8_t *wmap;           // [nbrick_tot][stage_cap] packed image shift of each staged particle
     int32_t *stotal;         // [nbrick_tot] staged particles per brick (> stage_cap: overflow)

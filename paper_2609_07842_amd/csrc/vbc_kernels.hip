@@ -626,7 +626,9 @@ __device__ void place_members(const Buffers &B, const RepDev &R, int r, int b,
         B.tags[ns] = key;
         B.types[ns] = B.type[o];
         B.lcells[ns] = (uint8_t)lc;
-        B.inv[R.o_off + key] = (int32_t)ns;
+        // caller index -> slot: read only for the bond partners of chains (a scattered
+        // write per particle, left out without bonds)
+        if (R.chain_len > 1) B.inv[R.o_off + key] = (int32_t)ns;
     }
     for (int lc = threadIdx.x; lc < S.ncb; lc += blockDim.x) {
         B.cstart[1][R.c_off + S.rank0 + lc] = (int32_t)(S.base + T.cpre[lc]);
