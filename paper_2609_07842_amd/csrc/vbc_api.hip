@@ -42,7 +42,7 @@ struct Offsets {
     size_t reps, brick_rep, wl0, wl1, wl_n, cell_rank, brick_rank0, cstart0, cstart1, ccnt0, ccnt1, bcnt0, bcnt1,
         bfill, x0, x1, v, Fst, xref, tag, type, lcell, xs, vs, tags, types, lcells, src, inv,
         smap, wmap, stotal, nl, nn, nd, sA, wcnt, wlst, part, flags, step, stats, bevals, bentries,
-        stamps, stamp_n, thermo;
+        stamps, stamp_n, thermo, tpend;
     size_t bytes;
 };
 
@@ -386,6 +386,7 @@ Offsets layout(const Caps &C, int precision, int nchunk, int stage_cap)
     o.stamps = carve(off, sizeof(unsigned long long) * STAMP_CAP);
     o.stamp_n = carve(off, sizeof(unsigned long long));
     o.thermo = carve(off, sizeof(double) * THERMO_WORDS * nr);
+    o.tpend = carve(off, sizeof(int32_t) * nr);
     o.bytes = off;
     return o;
 }
@@ -561,6 +562,7 @@ vbc_status make_handle(const Caps &C, const vbc_options &opt, bool pool, void *d
     B.stamps = at<unsigned long long>(d_ws, o.stamps);
     B.stamp_n = at<unsigned long long>(d_ws, o.stamp_n);
     B.thermo = at<double>(d_ws, o.thermo);
+    B.tpend = at<int32_t>(d_ws, o.tpend);
 
     hipError_t e = hipHostMalloc((void **)&h->up, sizeof(RepDev) * std::max(C.nrep, 1), hipHostMallocDefault);
     if (e == hipSuccess) {
@@ -726,14 +728,23 @@ static hipError_t launch_step(vbc_handle h, int c, const StepArgs &st, Mode mode
     if (e == hipSuccess)
         e = timed(h, VBC_K_COUNT, s, [&] { return launch_count(h->B, h->P, c, nullptr, 1, stats, s); });
     if (e == hipSuccess) e = timed(h, VBC_K_EMBED, s, [&] { return launch_embed(h->B, h->P, c, s); });
+    // with the sums on, the force pass leaves the step's per-brick energy and virial sums,
+    // which the next step's count pass adds (the call's last step: launch_thermo_flush)
+    StepArgs sa = st;
+    sa.acc = h->thermo ? 1 : 0;
     if (e == hipSuccess)
         e = timed(h, VBC_K_FORCE, s, [&] {
-            return launch_force(h->B, h->P, c, mode, h->thermo, st, nullptr, nullptr, s);
+            return launch_force(h->B, h->P, c, mode, h->thermo, sa, nullptr, nullptr, s);
         });
-    if (e == hipSuccess && h->thermo)
-        e = timed(h, VBC_K_REDUCE, s, [&] { return launch_thermo_acc(h->B, h->P, s); });
     if (e == hipSuccess && h->stamps) e = launch_stamp(h->B, s);
     return e;
+}
+
+// The energy and virial sums of a call's last step, added at the end of the call.
+static hipError_t launch_thermo_flush(vbc_handle h, hipStream_t s)
+{
+    if (!h->thermo) return hipSuccess;
+    return timed(h, VBC_K_REDUCE, s, [&] { return launch_thermo_acc(h->B, h->P, s); });
 }
 
 static hipError_t launch_kick(vbc_handle h, int c, const StepArgs &st, hipStream_t s)
@@ -781,6 +792,7 @@ static hipError_t get_graph(vbc_handle h, int kind, int nsteps, int c, const Ste
             cc ^= 1;
         }
         if (le == hipSuccess) le = launch_step(h, cc, st, MODE_LAST, nsteps - 1, h->cap_stream);
+        if (le == hipSuccess) le = launch_thermo_flush(h, h->cap_stream);
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->cap_stream, &g);
@@ -1251,6 +1263,7 @@ vbc_status vbc_step(vbc_handle h, int32_t nsteps, const vbc_integrator *it, hipS
     }
     // last step: closing half-kick only; its forces are kept for the next call
     VBC_TRY(h, launch_step(h, h->cur, st, MODE_LAST, k, s), "step");
+    VBC_TRY(h, launch_thermo_flush(h, s), "energy and virial sums");
     return VBC_OK;
 }
 

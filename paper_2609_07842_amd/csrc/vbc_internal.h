@@ -114,6 +114,8 @@ struct Buffers {
     unsigned long long *stamp_n; // [1] stamps written so far
     double *thermo;             // [nrep][THERMO_WORDS] steps accumulated, last step's
                                 // {U, W, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz}, their sums
+    int32_t *tpend;             // [nrep] 1: the last time step's per-brick energy and virial
+                                // sums (part) are not yet added to thermo
 };
 
 constexpr int THERMO_WORDS = 17;
@@ -157,6 +159,9 @@ enum Mode { MODE_EVAL = 0, MODE_MID = 1, MODE_LAST = 2 };
 
 struct StepArgs {
     int kind;               // VBC_NVE / VBC_LANGEVIN
+    int acc;                // a time step with the energy and virial sums on: the force pass
+                            // leaves its per-brick sums for the next count pass (or the call's
+                            // closing reduction) to add
     double dt, hdt;
     double c1, c2s;         // Langevin O-step coefficients
     uint64_t seed;

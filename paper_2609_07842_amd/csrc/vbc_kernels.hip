@@ -1278,6 +1278,9 @@ __device__ __forceinline__ void recount_window(const Buffers &B, const Launch &P
     }
 }
 
+__device__ __forceinline__ double replica_sum(const Buffers &B, const RepDev &R);
+__device__ __forceinline__ void thermo_add(const Buffers &B, const RepDev &R, int r);
+
 // STATS: also count the ordered pairs inside the interaction cutoff (the pair-evaluation
 // statistic); the step loop samples it on one step in eight.
 template <class Real, bool MULTI, bool STATS, bool ONE>
@@ -1298,6 +1301,9 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
     const RepDev &R = rep_of<ONE>(R1, B, r);
     int lb = b - R.b_off;
     if (lb == 0 && threadIdx.x == 0) atomicAnd(&B.flags[r], ~(uint32_t)VBC_FLAG_REBUILD);
+    // the replica's first brick adds the energy and virial sums the last time step's force
+    // pass left (with the sums on), after its own work
+    const int pend = lb == 0 ? B.tpend[r] : 0;
     R4 *spos = (R4 *)smem;
     const int64_t S_ = P.nslots;
     load_pairs<Real>(R, pt);
@@ -1320,6 +1326,7 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
             atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
             B.wcnt[b] = 0;
         }
+        if (pend) thermo_add(B, R, r);
         return;
     }
     const double *X = B.x[cur];
@@ -1423,6 +1430,7 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
             if (advance) B.step[r] += 1ull;
         }
     }
+    if (pend) thermo_add(B, R, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -1654,6 +1662,7 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     if (S.overflow) {
         if (threadIdx.x == 0) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_STAGE_OVERFLOW);
         if (THERMO && threadIdx.x < 8) B.part[(size_t)b * 8 + threadIdx.x] = 0.0;
+        if (THERMO && st.acc && lb == 0 && threadIdx.x == 0) B.tpend[r] = 1;
         return;
     }
     const double *X = B.x[cur];
@@ -1849,6 +1858,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
             for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
         }
         B.part[(size_t)b * 8 + threadIdx.x] = s;
+        // a time step's sums: added by the next count pass or the call's closing reduction
+        if (st.acc && lb == 0 && threadIdx.x == 0) B.tpend[r] = 1;
     }
 }
 
@@ -1916,26 +1927,44 @@ __global__ void k_reduce(Buffers B, int nrep, double *__restrict__ UW)
     if (threadIdx.x < 8) UW[r * 8 + threadIdx.x] = s;
 }
 
-// After a force pass with the sums on: each live replica's energy and virial of this step
-// (kept as the last step's) added to its running sums, and its step count raised by one.
-// A slot is live when its first brick is owned by it (retired descriptors stay behind).
-__global__ void k_thermo_acc(Buffers B, int nrep)
+// A time step's energy and virial of replica r (kept as the last step's) added to its
+// running sums from the per-brick sums its force pass left, and its step count raised by
+// one; the pending mark cleared.  Called by a whole workgroup.
+__device__ __forceinline__ void thermo_add(const Buffers &B, const RepDev &R, int r)
 {
-    const int r = blockIdx.x;
-    const RepDev &R = B.reps[r];
-    if (R.nbrick <= 0 || B.brick_rep[R.b_off] != r) return;
     const double s = replica_sum(B, R);
     if (threadIdx.x < 8) {
         double *T = B.thermo + (size_t)r * THERMO_WORDS;
         T[1 + threadIdx.x] = s;
         T[9 + threadIdx.x] += s;
-        if (threadIdx.x == 0) T[0] += 1.0;
+        if (threadIdx.x == 0) {
+            T[0] += 1.0;
+            B.tpend[r] = 0;
+        }
     }
+}
+
+// At the end of a call with the sums on: the last step's sums of every replica with sums
+// pending (a slot is live when its first brick is owned by it; retired descriptors stay
+// behind).
+__global__ void k_thermo_acc(Buffers B, int nrep)
+{
+    const int r = blockIdx.x;
+    const RepDev &R = B.reps[r];
+    if (!B.tpend[r]) return;
+    if (R.nbrick <= 0 || B.brick_rep[R.b_off] != r) {
+        if (threadIdx.x == 0) B.tpend[r] = 0;
+        return;
+    }
+    thermo_add(B, R, r);
 }
 
 __global__ void k_thermo_clear(Buffers B, int n)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) B.thermo[i] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        B.thermo[i] = 0.0;
+        if (i < n / THERMO_WORDS) B.tpend[i] = 0;
+    }
 }
 
 // Export the list of one replica as tag pairs (inspection and tests).
