@@ -1900,22 +1900,25 @@ __global__ void k_kick_drift(Buffers B, Launch P, int cur, StepArgs st)
 // Sum of the per-brick energy/virial partial sums of replica R over its bricks, in a fixed
 // order (strided per thread, then waves, then the wave totals in order); the result is
 // valid in threads 0..7 (one component each).
+// The eight sums of replica R's per-brick partial sums, in an order that does not depend on
+// the workgroup's size (the count pass and the closing reduction run it with different
+// sizes): lane l of the first wave adds bricks l, l + 64, ..., then the wave's lanes are
+// added in the fixed order of wave_sum.  Called by the whole workgroup; thread k < 8 gets
+// component k.
 __device__ __forceinline__ double replica_sum(const Buffers &B, const RepDev &R)
 {
-    __shared__ double red[8][1024 / VBC_WAVE];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < R.nbrick; b += blockDim.x)
-        for (int k = 0; k < 8; ++k) acc[k] += B.part[(size_t)(R.b_off + b) * 8 + k];
-    int wv = threadIdx.x / VBC_WAVE, ln = threadIdx.x % VBC_WAVE;
-    for (int k = 0; k < 8; ++k) {
-        double v = wave_sum(acc[k]);
-        if (ln == 0) red[k][wv] = v;
+    __shared__ double red[8];
+    if (threadIdx.x < VBC_WAVE) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = threadIdx.x; b < R.nbrick; b += VBC_WAVE)
+            for (int k = 0; k < 8; ++k) acc[k] += B.part[(size_t)(R.b_off + b) * 8 + k];
+        for (int k = 0; k < 8; ++k) {
+            const double v = wave_sum(acc[k]);
+            if (threadIdx.x == 0) red[k] = v;
+        }
     }
     __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x < 8)
-        for (int w = 0; w < (int)(blockDim.x / VBC_WAVE); ++w) s += red[threadIdx.x][w];
-    return s;
+    return threadIdx.x < 8 ? red[threadIdx.x] : 0.0;
 }
 
 // Per-replica totals from the per-brick partial sums, in brick order.

@@ -1,8 +1,8 @@
 """GPU tests of the per-step energy and virial (vbc_thermo) and of capturing the step
 graphs ahead of a call (vbc_step_prepare): the last step's energy and virial against the
 oracle at the GPU's final positions, the sums over steps against the oracle's trajectory,
-a replica's sums alone and in a pool bit for bit, and prepared calls bit for bit equal to
-unprepared ones."""
+a replica's sums alone and in a pool bit for bit, the sums independent of how the steps are
+split into calls, and prepared calls bit for bit equal to unprepared ones."""
 import numpy as np
 import pytest
 
@@ -85,6 +85,30 @@ def test_thermo_alone_and_in_a_pool_bitwise():
     assert t_mix[ra]["steps"] == 24 and t_mix[rb]["steps"] == 24
     assert np.array_equal(t_alone["last"], t_mix[ra]["last"])
     assert np.array_equal(t_alone["sum"], t_mix[ra]["sum"])
+
+
+def test_thermo_sums_do_not_depend_on_the_call_split():
+    # a step's sums are added by the next step's count pass, the call's last step's by the
+    # closing reduction: both must give the same bits, so one call of 90 steps (graphs of
+    # eight steps), three of 30 (whole-call graphs) and 90 of one step agree exactly
+    vbc = _vbc()
+    wl = W.fluid(2000, 0.4, 3.0, E_a=5.0, seed=34)
+    integ = dict(integrator="langevin", dt=0.005, kT=1.0, gamma=0.1, seed=6)
+    res = []
+    for split in ([90], [30, 30, 30], [1] * 90):
+        s = vbc.System(vbc.replica(wl.N, wl.L, wl.params), precision="fp32", block=256)
+        s.set_state(wl.x, wl.v)
+        s.thermo(True)
+        for n in split:
+            s.step(n, **integ)
+        th = s.thermo_read()[0]
+        s.check()
+        res.append((th["steps"], th["last"], th["sum"]))
+        s.close()
+    for steps, last, sums in res[1:]:
+        assert steps == res[0][0] == 90
+        assert np.array_equal(last, res[0][1])
+        assert np.array_equal(sums, res[0][2])
 
 
 @pytest.mark.parametrize("nsteps", [20, 100])
