@@ -1701,7 +1701,9 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         const R2 sai = MULTI ? ssa[t] : R2{pi.w, scA[t]};
         int ti = MULTI ? (int)pi.w : 0;
         const Real cai = p0.c_a * sai.x;
-        Real fx = 0, fy = 0, fz = 0, ei = 0;
+        // ei: pair energies (several types), or with one type sum tc^2 and ea sum s_j q_a^2,
+        // which E_r and E_a s_i scale once per particle
+        Real fx = 0, fy = 0, fz = 0, ei = 0, ea = 0;
         Real wxx = 0, wyy = 0, wzz = 0, wxy = 0, wxz = 0, wyz = 0;
         for_each_neighbour(B.nl, S_, i, B.nn[i], [&](int u) {
             int ex = 0;  // pair excluded from counting and attraction (chain neighbours)
@@ -1754,15 +1756,16 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
                 Real t = fma(sai.y + cAj, g, cai * sj * uu * qq);
                 phr = fma(t, rinv, pr);
                 if (THERMO) {
-                    Real tc = fmax(fma(-r2, p0.inv_rr2, Real(1)), Real(0));
-                    ep = p0.E_r * tc * tc - p0.E_a * (sai.x * sj) * qq * qq;
+                    const Real tc = fmax(fma(-r2, p0.inv_rr2, Real(1)), Real(0));
+                    ei = fma(tc, tc, ei);
+                    ea = fma(sj * qq, qq, ea);
                 }
             }
             fx -= phr * dx;
             fy -= phr * dy;
             fz -= phr * dz;
             if (THERMO) {
-                ei += ep;
+                if (MULTI) ei += ep;
                 wxx -= phr * dx * dx;
                 wyy -= phr * dy * dy;
                 wzz -= phr * dz * dz;
@@ -1804,7 +1807,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
         }
         if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) bad = true;
         if (THERMO) {
-            double e_i = 0.5 * (double)ei + eb;
+            const Real e_pair = MULTI ? ei : p0.E_r * ei - p0.E_a * sai.x * ea;
+            double e_i = 0.5 * (double)e_pair + eb;
             acc[0] += e_i;
             acc[2] += 0.5 * (double)wxx + wb[1];
             acc[3] += 0.5 * (double)wyy + wb[2];
