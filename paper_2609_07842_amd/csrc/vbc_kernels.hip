@@ -156,6 +156,35 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Eight sums over the wave at once.  At each of the first three halvings a lane keeps half
+// of its values and trades the other half with the lane 32, 16 or 8 away, so that from
+// then on every lane carries one value, which three more exchanges finish: ten shuffles
+// instead of the 48 of eight separate sums.  Returns, in lane L, the total of value
+// 4 b5 + 2 b4 + b3 (the bits of L): value k's total is in lane 8k.  The order of the
+// additions is fixed.
+__device__ __forceinline__ double wave_sum8(const double (&a)[8])
+{
+    const int lane = threadIdx.x % VBC_WAVE;
+    double s[4], t[2];
+    bool hi = lane & 32;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double keep = hi ? a[k + 4] : a[k], give = hi ? a[k] : a[k + 4];
+        s[k] = keep + __shfl_xor(give, 32, VBC_WAVE);
+    }
+    hi = lane & 16;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double keep = hi ? s[k + 2] : s[k], give = hi ? s[k] : s[k + 2];
+        t[k] = keep + __shfl_xor(give, 16, VBC_WAVE);
+    }
+    hi = lane & 8;
+    double u = (hi ? t[1] : t[0]) + __shfl_xor(hi ? t[0] : t[1], 8, VBC_WAVE);
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) u += __shfl_xor(u, o, VBC_WAVE);
+    return u;
+}
+
 // Exclusive scan of a[0..n) in place by the first wave; returns the total (valid in the
 // first wave).  Call from all threads of the block between barriers.
 __device__ __forceinline__ int wave0_exclusive_scan(int *a, int n)
@@ -729,7 +758,6 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     __shared__ int nmem_s;
     int b;
     if (!brick_of_block(P, B, b)) return;
-    const MapFirst mf = map_prefetch(B, b, P.stage_cap);
     // replica 0's flags read beside the owner: with one replica (the usual case) the test
     // that ends most launches needs no dependent read
     const uint32_t fl0 = B.flags[0];
@@ -738,6 +766,9 @@ __global__ void k_resort(Buffers B, Launch P, int cur)
     if (r < 0) return;
     const uint32_t fl = r == 0 ? fl0 : B.flags[r];
     if (!(fl & VBC_FLAG_REBUILD) || (fl & FLAG_FULL)) return;
+    // the staging map's first entries are read only once a build is due: a launch on a
+    // step without a build (most steps) then reads nothing but the flags
+    const MapFirst mf = map_prefetch(B, b, P.stage_cap);
     const RepDev &R = B.reps[r];
     int lb = b - R.b_off;
     int nh_cap = (P.nh_max + 3) & ~3;
@@ -1845,10 +1876,8 @@ __global__ void k_force(Buffers B, Launch P, int cur, int mode, StepArgs st,
     if (mv) moved = 1;
     if (THERMO) {
         int wv = threadIdx.x / VBC_WAVE, ln = threadIdx.x % VBC_WAVE;
-        for (int k = 0; k < 8; ++k) {
-            double v = wave_sum(acc[k]);
-            if (ln == 0) red[k][wv] = v;
-        }
+        const double v = wave_sum8(acc);
+        if ((ln & 7) == 0) red[ln >> 3][wv] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0 && moved) atomicOr(&B.flags[r], (uint32_t)VBC_FLAG_REBUILD);
