@@ -1336,6 +1336,9 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
     // pass left (with the sums on), after its own work
     const int pend = lb == 0 ? B.tpend[r] : 0;
     R4 *spos = (R4 *)smem;
+    constexpr bool SOA = !MULTI && sizeof(Real) == 4;
+    float2 *sxy = (float2 *)smem;
+    float *sza = (float *)(sxy + P.stage_cap + 1);
     const int64_t S_ = P.nslots;
     load_pairs<Real>(R, pt);
     if (threadIdx.x == 0) {
@@ -1363,9 +1366,23 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
     const double *X = B.x[cur];
     stage_map4(B, b, P.stage_cap, S, mf, [&](int t, int src, int w, bool ok) {
         const R4 p = local_pos<Real>(R, S, X, S_, src, w, MULTI ? B.type[src] : 0);
-        if (ok) spos[t] = p;
+        if (ok) {
+            if (SOA) {
+                sxy[t] = make_float2((float)p.x, (float)p.y);
+                sza[t] = (float)p.z;
+            } else {
+                spos[t] = p;
+            }
+        }
     });
-    if (threadIdx.x == 0) spos[P.stage_cap] = dummy_pos<R4>();
+    if (threadIdx.x == 0) {
+        if (SOA) {
+            sxy[P.stage_cap] = make_float2(1.0e6f, 1.0e6f);
+            sza[P.stage_cap] = 1.0e6f;
+        } else {
+            spos[P.stage_cap] = dummy_pos<R4>();
+        }
+    }
     __syncthreads();
 
     const PairR<Real> p0 = pt[0];
@@ -1377,7 +1394,16 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
     unsigned long long evals = 0;
     for (int t = threadIdx.x; t < S.n_own; t += blockDim.x) {
         int64_t i = S.base + t;
-        R4 pi = spos[t];
+        R4 pi;
+        if (SOA) {
+            const float2 q = sxy[t];
+            pi.x = q.x;
+            pi.y = q.y;
+            pi.z = sza[t];
+            pi.w = 0;
+        } else {
+            pi = spos[t];
+        }
         int ti = MULTI ? (int)pi.w : 0;
         int inside = 0;
         double n = 0.0;
@@ -1391,7 +1417,16 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8))) k_count(Buffers B, Launc
                 ex = u >> 15;
                 u &= 0x7fff;
             }
-            R4 pj = spos[u];
+            R4 pj;
+            if (SOA) {
+                const float2 q = sxy[u];
+                pj.x = q.x;
+                pj.y = q.y;
+                pj.z = sza[u];
+                pj.w = 0;
+            } else {
+                pj = spos[u];
+            }
             Real dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             Real r2 = dx * dx + dy * dy + dz * dz;
             if (STATS) inside += (r2 < p0.rc2) ? 1 : 0;
@@ -2660,7 +2695,7 @@ size_t lds_bytes_nlist(const Launch &P)
 }
 size_t lds_bytes_count(const Launch &P)
 {
-    return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : 16);
+    return (size_t)(P.stage_cap + 1) * (P.precision == VBC_FP64 ? 32 : (P.multi ? 16 : 12));
 }
 size_t lds_bytes_embed(const Launch &P) { (void)P; return 0; }
 // bond tests (observables, clusters): FP32 staging, then the slots or the brick's forest
