@@ -14,7 +14,8 @@ due, count pass, sparse dU/dn pass, force pass with the fused integrator update.
 Prints ONE JSON line.  `value` is pair evaluations per second (ordered pairs inside the
 interaction cutoff handled per step, times steps per second); timesteps/s is reported
 beside it.  `roofline` is the dominant kernel's algorithmic bytes per launch over its
-mean duration, timed with HIP events on the launch stream inside the timed region.
+mean duration, timed with HIP events that the kernels' own dispatches record
+(hipExtLaunchKernel) on the launch stream, in a region of the timed trajectory.
 `serving` is the request stream: 256 independent simulations (N log-uniform in
 [10^3, 2x10^5], valency 1..6, well depth 2..10 kT, density 0.3, 1000 Langevin steps each)
 arriving as a Poisson stream at 0.8x the measured batched capacity, served by continuous
@@ -292,7 +293,7 @@ def run_one(W, vbc, torch, f, steps, warmup, seed, profile=True, rho_max=0.0, re
                   "what": "every step also sums the pair energies and the virial (scalar and "
                           "tensor) per brick in FP64 and reduces them per replica"}
         # a third region of K steps continuing the same trajectory, every kernel launched
-        # individually between HIP events on the launch stream
+        # individually, its dispatch recording a pair of HIP events on the launch stream
         s.profile(True, max_launches=steps + 8)
         st2 = s.stats()[0]
         torch.cuda.synchronize()
@@ -510,9 +511,11 @@ def main():
                 "achievable_copy_GBs": copy_gbs,
                 "frac_of_copy": kd["achieved_GBs"] / copy_gbs if kd.get("achieved_GBs") else None,
                 "per_kernel_frac": {k: v.get("frac") for k, v in kernels.items() if v.get("frac")},
-                "timing": "HIP events on the launch stream around every launch of each kernel class "
-                          "in a third region of K steps (individual launches instead of step graphs); "
-                          "the list build's bytes are one build's, over its time per build",
+                "timing": "HIP events recorded by each kernel class's own dispatches "
+                          "(hipExtLaunchKernel: start of its first kernel, end of its last) on the "
+                          "launch stream, in a third region of K steps (individual launches instead "
+                          "of step graphs); the list build's bytes are one build's, over its time "
+                          "per build",
                 "ms_per_step_event_region": 1e3 * main_run["elapsed_prof"] / K}
     # whole-step view: all kernels' algorithmic bytes per step over the step time
     step_bytes = (kernel_bytes("count", wl.N, main_run["kbar"], "fp32")

@@ -305,8 +305,10 @@ typedef struct {
 } vbc_stats;
 vbc_status vbc_get_stats(vbc_handle h, hipStream_t s, vbc_stats *out /* host [slots] */);
 
-/* Kernel timing with HIP events recorded on the launch stream around every launch of each
- * kernel class, for at most max_launches launches per class (enable = 0 switches it off).
+/* Kernel timing with HIP events that each launch of a kernel class records from its own
+ * dispatches (hipExtLaunchKernel: the start of the class's first kernel and the end of its
+ * last, with no marker packets between them), on the launch stream, for at most
+ * max_launches launches per class (enable = 0 switches it off).
  * Classes: 0 list build (its five kernels together), 1 count, 2 embed, 3 force,
  * 4 first-step kick, 5 reductions.  vbc_profile_read synchronises s and returns, per
  * class, the summed milliseconds and the number of timed launches, then resets them. */

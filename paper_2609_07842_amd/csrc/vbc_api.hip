@@ -106,16 +106,20 @@ template <class Fn>
 static hipError_t timed(vbc_handle h, int kind, hipStream_t s, Fn &&fn)
 {
     bool on = h->prof && h->prof_n[kind] < h->prof_max;
-    if (on) {
-        hipError_t e = hipEventRecord(h->ev[kind][0][h->prof_n[kind]], s);
-        if (e != hipSuccess) return e;
-    }
+    if (!on) return fn();
+    // the pass's own dispatches record the events (no marker packets around it)
+    hipEvent_t e0 = h->ev[kind][0][h->prof_n[kind]], e1 = h->ev[kind][1][h->prof_n[kind]];
+    set_launch_events(e0, e1);
     hipError_t e = fn();
+    const int used = launch_events_used();
+    set_launch_events(nullptr, nullptr);
     if (e != hipSuccess) return e;
-    if (on) {
-        e = hipEventRecord(h->ev[kind][1][h->prof_n[kind]], s);
-        h->prof_n[kind]++;
+    if (used == 0) {
+        // nothing launched: an empty interval
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
     }
+    if (e == hipSuccess) h->prof_n[kind]++;
     return e;
 }
 

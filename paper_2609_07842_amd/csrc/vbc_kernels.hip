@@ -21,6 +21,7 @@
 // Data flow of one workgroup in a pass: it owns one brick; it stages its own particles and
 // the halo into LDS in a brick-local frame, then sweeps each own particle's list (16-bit
 // indices into the staging order, eight per 16-byte chunk) reading neighbours from LDS.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -2710,6 +2711,33 @@ size_t lds_bytes_force(const Launch &P)
     return (size_t)(P.stage_cap + 1) * real * (P.multi ? 6 : 5);
 }
 
+namespace {
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+thread_local int g_ev_used = 0;
+
+// A launch of a timed pass: through hipExtLaunchKernel while timing events are set.
+template <typename... P, typename... A>
+inline void tlaunch(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s, A... a)
+{
+    if (g_ev_stop) {
+        hipExtLaunchKernelGGL(k, grid, block, (std::uint32_t)lds, s, g_ev_start, g_ev_stop, 0u, a...);
+        g_ev_start = nullptr;
+        ++g_ev_used;
+    } else {
+        k<<<grid, block, lds, s>>>(a...);
+    }
+}
+}  // namespace
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    g_ev_start = start;
+    g_ev_stop = stop;
+    g_ev_used = 0;
+}
+
+int launch_events_used() { return g_ev_used; }
+
 hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
                             const double *x, const double *v, const int32_t *type,
                             int64_t in_off, int64_t in_stride, uint64_t step0, hipStream_t s)
@@ -2762,9 +2790,9 @@ hipError_t launch_stamp(const Buffers &B, hipStream_t s)
 hipError_t launch_full_build(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
                              hipStream_t s)
 {
-    if (n > 0) k_gbin<<<blocks_for(n, 256), 256, 0, s>>>(B, P.nslots, cur, r);
-    k_gsort<<<brick_grid(P.nb_launch), P.block, sort_bytes(P), s>>>(B, P, cur);
-    k_nlist<<<brick_grid(P.nb_launch), P.block, lds_bytes_nlist(P), s>>>(B, P, cur);
+    if (n > 0) tlaunch(k_gbin, blocks_for(n, 256), 256, 0, s, B, P.nslots, cur, r);
+    tlaunch(k_gsort, brick_grid(P.nb_launch), P.block, sort_bytes(P), s, B, P, cur);
+    tlaunch(k_nlist, brick_grid(P.nb_launch), P.block, lds_bytes_nlist(P), s, B, P, cur);
     return hipGetLastError();
 }
 
@@ -2774,11 +2802,11 @@ hipError_t launch_rebuild(const Buffers &B, const Launch &P, int cur, hipStream_
 {
     Launch Q = P;
     if (P.list >= 0) {
-        k_worklist<<<1, 1024, 0, s>>>(B, P.nrep);
+        tlaunch(k_worklist, 1, 1024, 0, s, B, P.nrep);
         Q.list = 1;
     }
-    k_resort<<<brick_grid(Q.nb_launch), Q.block, lds_bytes_sort(Q), s>>>(B, Q, cur);
-    k_nlist<<<brick_grid(Q.nb_launch), Q.block, lds_bytes_nlist(Q), s>>>(B, Q, cur);
+    tlaunch(k_resort, brick_grid(Q.nb_launch), Q.block, lds_bytes_sort(Q), s, B, Q, cur);
+    tlaunch(k_nlist, brick_grid(Q.nb_launch), Q.block, lds_bytes_nlist(Q), s, B, Q, cur);
     return hipGetLastError();
 }
 
@@ -2790,12 +2818,12 @@ static void launch_count_t(const Buffers &B, const Launch &P, int cur, double *n
     unsigned g = brick_grid(P.nb_launch);
     if (P.one) {
         const OneRep<true> R1{*P.one};
-        if (stats) k_count<Real, MULTI, true, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
-        else k_count<Real, MULTI, false, true><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+        if (stats) tlaunch(k_count<Real, MULTI, true, true>, g, P.block, lds, s, B, P, cur, n_out, advance, R1);
+        else tlaunch(k_count<Real, MULTI, false, true>, g, P.block, lds, s, B, P, cur, n_out, advance, R1);
     } else {
         const OneRep<false> R1{0};
-        if (stats) k_count<Real, MULTI, true, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
-        else k_count<Real, MULTI, false, false><<<g, P.block, lds, s>>>(B, P, cur, n_out, advance, R1);
+        if (stats) tlaunch(k_count<Real, MULTI, true, false>, g, P.block, lds, s, B, P, cur, n_out, advance, R1);
+        else tlaunch(k_count<Real, MULTI, false, false>, g, P.block, lds, s, B, P, cur, n_out, advance, R1);
     }
 }
 
@@ -2820,11 +2848,11 @@ hipError_t launch_embed(const Buffers &B, const Launch &P, int cur, hipStream_t 
     const int bs = EMBED_WAVES * VBC_WAVE;
     size_t lds = 0;
     if (P.precision == VBC_FP64) {
-        if (multi) k_embed<double, true><<<g, bs, lds, s>>>(B, P, cur);
-        else k_embed<double, false><<<g, bs, lds, s>>>(B, P, cur);
+        if (multi) tlaunch(k_embed<double, true>, g, bs, lds, s, B, P, cur);
+        else tlaunch(k_embed<double, false>, g, bs, lds, s, B, P, cur);
     } else {
-        if (multi) k_embed<float, true><<<g, bs, lds, s>>>(B, P, cur);
-        else k_embed<float, false><<<g, bs, lds, s>>>(B, P, cur);
+        if (multi) tlaunch(k_embed<float, true>, g, bs, lds, s, B, P, cur);
+        else tlaunch(k_embed<float, false>, g, bs, lds, s, B, P, cur);
     }
     return hipGetLastError();
 }
@@ -2838,15 +2866,15 @@ static void launch_force_t(const Buffers &B, const Launch &P, int cur, Mode mode
     if (P.one) {
         const OneRep<true> R1{*P.one};
         if (thermo)
-            k_force<Real, MULTI, true, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+            tlaunch(k_force<Real, MULTI, true, true>, g, P.block, lds, s, B, P, cur, (int)mode, st, F_out, e_out, R1);
         else
-            k_force<Real, MULTI, false, true><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+            tlaunch(k_force<Real, MULTI, false, true>, g, P.block, lds, s, B, P, cur, (int)mode, st, F_out, e_out, R1);
     } else {
         const OneRep<false> R1{0};
         if (thermo)
-            k_force<Real, MULTI, true, false><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+            tlaunch(k_force<Real, MULTI, true, false>, g, P.block, lds, s, B, P, cur, (int)mode, st, F_out, e_out, R1);
         else
-            k_force<Real, MULTI, false, false><<<g, P.block, lds, s>>>(B, P, cur, (int)mode, st, F_out, e_out, R1);
+            tlaunch(k_force<Real, MULTI, false, false>, g, P.block, lds, s, B, P, cur, (int)mode, st, F_out, e_out, R1);
     }
 }
 
