@@ -112,6 +112,7 @@ static hipError_t timed(vbc_handle h, int kind, hipStream_t s, Fn &&fn)
     set_launch_events(e0, e1);
     hipError_t e = fn();
     const int used = launch_events_used();
+    if (e == hipSuccess) e = launch_events_error();
     set_launch_events(nullptr, nullptr);
     if (e != hipSuccess) return e;
     if (used == 0) {

@@ -171,9 +171,11 @@ struct StepArgs {
 // list build, count, dU/dn and force passes dispatch through hipExtLaunchKernel, which takes
 // the events' timestamps from the dispatches themselves (start at the first kernel, stop at
 // each, so the last one's end wins), with no marker packets between the kernels.
-// launch_events_used() counts the launches that took them since the last set.
+// launch_events_used() counts the launches that took them since the last set, and
+// launch_events_error() returns the first error one of those launches returned.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 int launch_events_used();
+hipError_t launch_events_error();
 
 // host-side launchers (vbc_kernels.hip).  Brick kernels cover the bricks
 // [P.b_lo, P.b_lo + P.nb_launch), or with P.list >= 0 the work lists that launch_rebuild and

@@ -26,6 +26,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <tuple>
 
 #include "vbc_internal.h"
 
@@ -2714,13 +2715,25 @@ size_t lds_bytes_force(const Launch &P)
 namespace {
 thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 thread_local int g_ev_used = 0;
+thread_local hipError_t g_ev_err = hipSuccess;
 
-// A launch of a timed pass: through hipExtLaunchKernel while timing events are set.
+// A launch of a timed pass: through hipExtLaunchKernel while timing events are set (its
+// error, if any, is kept for launch_events_used's caller), else the plain launch.
 template <typename... P, typename... A>
 inline void tlaunch(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s, A... a)
 {
     if (g_ev_stop) {
-        hipExtLaunchKernelGGL(k, grid, block, (std::uint32_t)lds, s, g_ev_start, g_ev_stop, 0u, a...);
+        std::tuple<std::decay_t<P>...> args(a...);
+        void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+        std::apply(
+            [&](auto &...x) {
+                int n = 0;
+                ((ptrs[n++] = (void *)&x), ...);
+            },
+            args);
+        const hipError_t e = hipExtLaunchKernel((const void *)k, grid, block, ptrs, lds, s, g_ev_start,
+                                                g_ev_stop, 0);
+        if (e != hipSuccess && g_ev_err == hipSuccess) g_ev_err = e;
         g_ev_start = nullptr;
         ++g_ev_used;
     } else {
@@ -2734,9 +2747,12 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop)
     g_ev_start = start;
     g_ev_stop = stop;
     g_ev_used = 0;
+    g_ev_err = hipSuccess;
 }
 
 int launch_events_used() { return g_ev_used; }
+
+hipError_t launch_events_error() { return g_ev_err; }
 
 hipError_t launch_set_state(const Buffers &B, const Launch &P, int cur, int r, int64_t n,
                             const double *x, const double *v, const int32_t *type,
