@@ -107,6 +107,38 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(xa, xb) and np.array_equal(va, vb)
 
 
+def test_kernel_timing_leaves_the_trajectory_and_times_every_pass():
+    """The timing mode launches each pass through hipExtLaunchKernel with a pair of events
+    that its dispatches record: same bits as the step graphs, one timed launch per pass and
+    step, and per-pass times that fit inside the wall time of the steps."""
+    import time
+    vbc = _vbc()
+    wl = W.small_fluid(N=3000, rho=0.5, f=4.0)
+    out = []
+    for timing in (False, True):
+        s = vbc.System(vbc.replica(wl.N, wl.L, wl.params), precision="fp32")
+        s.set_state(wl.x, wl.v)
+        s.step(20, integrator="langevin", seed=5)
+        if timing:
+            s.profile(True, 1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(40, integrator="langevin", seed=5)
+        torch.cuda.synchronize()
+        wall_ms = 1e3 * (time.perf_counter() - t0)
+        s.check()
+        out.append([t.cpu().numpy().copy() for t in s.get_state()])
+        if timing:
+            prof = s.profile_read()
+            print(f"[timing] wall {wall_ms:.3f} ms, " +
+                  ", ".join(f"{k} {v[0]:.3f} ms/{v[1]}" for k, v in prof.items()), flush=True)
+            for k in ("build", "count", "embed", "force"):
+                assert prof[k][1] == 40, (k, prof[k])
+                assert prof[k][0] > 0.0, (k, prof[k])
+            assert sum(prof[k][0] for k in ("build", "count", "embed", "force")) <= wall_ms
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_stage_capacity_overflow_reported():
     vbc = _vbc()
     N = 3000
