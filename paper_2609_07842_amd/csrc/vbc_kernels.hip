@@ -1643,8 +1643,8 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     const int64_t base = R.p_off + (int64_t)lb * R.bcap;
     const int t_first = B.wlst[base + lane / CHUNK];  // for eight lanes per particle
     // eight lanes per particle when the first wave takes all of the brick's window particles
-    // at once; with more of them, four lanes each over every wave of the workgroup, so that
-    // up to EMBED_WAVES x 16 are in flight
+    // at once; up to EMBED_WAVES x 8 of them, eight lanes each over every wave; with more,
+    // four lanes each over every wave, so that up to EMBED_WAVES x 16 are in flight
     const bool one = nw <= VBC_WAVE / CHUNK;
     if (one && wv > 0) return;
     PairR<Real> *pt = ptab[wv];
@@ -1661,6 +1661,11 @@ __global__ void k_embed(Buffers B, Launch P, int cur)
     if (one) {
         embed_brick<CHUNK, Real, MULTI>(B, P, R, pt, b, base, nw, lane, lane / CHUNK, VBC_WAVE / CHUNK,
                                         t_first, cur);
+    } else if (nw <= EMBED_WAVES * (VBC_WAVE / CHUNK)) {
+        // up to 32: eight lanes each over every wave, all of them in one round
+        constexpr int G = VBC_WAVE / CHUNK;
+        embed_brick<CHUNK, Real, MULTI>(B, P, R, pt, b, base, nw, lane, wv * G + lane / CHUNK,
+                                        EMBED_WAVES * G, -1, cur);
     } else {
         constexpr int G = VBC_WAVE / 4;  // groups of four lanes per wave
         embed_brick<4, Real, MULTI>(B, P, R, pt, b, base, nw, lane, wv * G + lane / 4, EMBED_WAVES * G,
