@@ -63,6 +63,9 @@ CASES = [
     # so the dU/dn pass spreads them over every wave of its workgroup, and the count pass
     # recounts them in FP64
     ("window_heavy_f10", 4000, W.box_length(4000, 0.5), W.vbc_params(E_a=5.0, f=10.0)),
+    # 12 to 31 window particles in each of the eight bricks: the dU/dn pass's eight lanes per
+    # particle over all four waves of its workgroup
+    ("window_mid_f6", 4000, W.box_length(4000, 0.5), W.vbc_params(E_a=5.0, f=6.0)),
 ]
 
 
