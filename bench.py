@@ -350,22 +350,19 @@ def run_melt(W, vbc, torch, steps, warmup, seed):
     stickers, FP32 pair arithmetic, Langevin kT = 1.  The random-walk start packs beads at
     bond distance and overlapping chains, so the first `warmup` steps run in a layout sized
     for local densities up to 2 with a long list (k_max 256); the timed handle is then laid
-    out for the relaxed melt (bricks of 3^3 cells keep the dense staging within LDS)."""
-    wl = W.polymer_melt(seed=seed)
-    integ = dict(integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=seed)
-
-    def make(**opts):
-        return vbc.System(vbc.replica(wl.N, wl.L, wl.params, mask=wl.mask, chain_len=50,
-                                      k_bond=wl.k_bond, r0_bond=wl.r0, skin=W.SKIN),
-                          precision="fp32", brick=3, **opts)
-    s = make(k_max=256, rho_max=2.0)
-    s.set_state(wl.x, wl.v, types=wl.types)
-    s.step(warmup, **integ)
-    s.check()
-    x, v = (t.contiguous() for t in s.get_state())
-    s.close()
-    del s
-    s = make()
+    out for the relaxed melt, with the brick and workgroup size the autotuner cached for it
+    (bricks of 3^3 cells, the default, keep the dense staging within LDS)."""
+    from paper_2609_07842_amd import tune
+    wl, x, v = tune.relaxed_melt(seed=seed, warmup=warmup)
+    integ = tune.melt_integrator(wl)
+    key = tune.melt_key("fp32")
+    lay = tune.lookup(key)
+    if lay is None:
+        print(f"[bench] melt: default layout (autotune cache: {tune.stale(key)})", file=sys.stderr, flush=True)
+        lay = dict(brick=3)
+    else:
+        print(f"[bench] melt: tuned layout {lay}", file=sys.stderr, flush=True)
+    s = tune.melt_system(wl, "fp32", **lay)
     s.set_state(x, v, types=wl.types)
     s.step(200, **integ)
     s.check()
