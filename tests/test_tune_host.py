@@ -29,6 +29,8 @@ def test_keys_name_device_and_workload():
     assert k == "gfx950x256CU|fluid|N=1000000|rho=0.5|fp32"
     kp = tune.pool_key(serve.ServerConfig(), device="gfx950x256CU")
     assert kp.startswith("gfx950x256CU|pool|rho=0.3|N=1000-200000|fp32")
+    km = tune.melt_key("fp32", device="gfx950x256CU")
+    assert km == "gfx950x256CU|melt|N=1000000|rho=0.85|fp32"
 
 
 def test_committed_choices_are_valid_layouts():
