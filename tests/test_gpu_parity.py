@@ -155,6 +155,8 @@ def test_fp32_mixed_parity(name, N, L, params):
     esc = np.abs(ref["e"]).sum()
     assert abs(UW[0, 0] - ref["U"]) <= 1e-5 * max(1.0, esc)
     assert abs(UW[0, 1] - ref["W"]) <= 1e-5 * max(1.0, np.abs(ref["W"]) + esc)
+    # the virial tensor (xx, yy, zz, xy, xz, yz) to the same bar
+    assert np.abs(UW[0, 2:] - ref["Wt"]).max() <= 1e-5 * max(1.0, np.abs(ref["W"]) + esc)
 
 
 @pytest.mark.parametrize("block", [128, 256, 1024])
