@@ -23,10 +23,13 @@ def _min_image(d, L):
     return d - L * np.rint(d / L)
 
 
+@pytest.mark.parametrize("case", ["small", "window_mid"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_thermo_matches_oracle(precision, tol):
+def test_thermo_matches_oracle(precision, tol, case):
     vbc = _vbc()
-    wl = W.small_fluid()
+    # small: N = 1000 at density 0.3, f = 2; window_mid: N = 4000 at density 0.5, f = 6,
+    # where tens of particles per brick sit in a switching window (chain-rule terms)
+    wl = W.small_fluid() if case == "small" else W.small_fluid(N=4000, rho=0.5, f=6.0)
     s = vbc.System(vbc.replica(wl.N, wl.L, wl.params), precision=precision)
     s.set_state(wl.x, wl.v)
     s.thermo(True)
