@@ -307,16 +307,18 @@ def test_trajectory_parity_fp64(kind):
     assert _normwise(F.cpu().numpy(), Fr) <= 1e-9
 
 
-def test_trajectory_parity_fp32_timed_kernel():
+@pytest.mark.parametrize("case", ["small", "window_mid"])
+def test_trajectory_parity_fp32_timed_kernel(case):
     """The time step as the benchmark runs it (FP32 pair arithmetic, the integrator fused
     into the force pass, whole-call step graph): 1000 particles at density 0.3, valency 2,
-    well depth 5, 50 BAOAB Langevin steps with the shared counter-based noise, against the
+    well depth 5 (and 4000 at density 0.5, valency 6, with tens of window particles per
+    brick), 50 BAOAB Langevin steps with the shared counter-based noise, against the
     FP64 oracle's trajectory.  The FP32 forces are within about 3e-6 of the exact ones
     (normwise), so over 50 steps of dt = 0.005 the positions may drift apart by about
     dt^2 |dF| per step, amplified by the chaotic dynamics; the bound 2e-5 on every
     coordinate (box edge 14.9) holds that with a margin, and the velocities are held to
     2e-4 (thermal speed ~1)."""
-    wl = W.small_fluid()
+    wl = W.small_fluid() if case == "small" else W.small_fluid(N=4000, rho=0.5, f=6.0)
     s = _system(wl.N, wl.L, wl.params, precision="fp32")
     s.set_state(wl.x, wl.v)
     s.step(50, integrator="langevin", dt=0.005, kT=1.0, gamma=0.1, seed=13)
@@ -326,7 +328,7 @@ def test_trajectory_parity_fp32_timed_kernel():
                      gamma=0.1, seed=13)
     dx = np.abs(_min_image(x - ref["x"], wl.L)).max()
     dv = np.abs(v - ref["v"]).max()
-    print(f"[traj fp32] max |dx| {dx:.2e}, max |dv| {dv:.2e}", flush=True)
+    print(f"[traj fp32] {case} max |dx| {dx:.2e}, max |dv| {dv:.2e}", flush=True)
     assert dx <= 2e-5
     assert dv <= 2e-4
 
