@@ -237,19 +237,23 @@ def test_sampled_parity_at_full_size(N, rho, f, nsample):
     assert np.abs(F.sum(axis=0)).max() <= 1e-5 * np.linalg.norm(F, axis=1).max() * np.sqrt(N)
 
 
-def test_sampled_parity_headline_after_steps():
+@pytest.mark.parametrize("f,steps,rho_max", [(4.0, 500, 0.0), (6.0, 2000, 0.9)])
+def test_sampled_parity_headline_after_steps(f, steps, rho_max):
     """The headline fluid (N = 10^6, density 0.5, f = 4, FP32 pair arithmetic) after 500
-    Langevin steps of its benchmark trajectory, in the benchmark's launch configuration:
-    counts and forces of particles inside a switching window (their counts are summed again
-    in FP64), of their neighbours and of uniformly drawn particles against the oracle's local
-    evaluation at the GPU's own positions."""
+    Langevin steps of its benchmark trajectory, in the benchmark's launch configuration,
+    and the same fluid at f = 6 after 2000 steps (condensing, several per cent of the
+    particles in a switching window; laid out for local densities up to 0.9 as in the
+    valency sweep): counts and forces of particles inside a switching window (their counts
+    are summed again in FP64), of their neighbours and of uniformly drawn particles against
+    the oracle's local evaluation at the GPU's own positions."""
     from scipy.spatial import cKDTree
     vbc = _vbc()
-    print("[sampled headline after 500 steps] N=1000000", flush=True)
-    wl = W.headline()
-    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32")
+    print(f"[sampled headline f={f:g} after {steps} steps] N=1000000", flush=True)
+    wl = W.headline(f=f)
+    s = vbc.System(vbc.replica(wl.N, wl.L, wl.params, skin=W.SKIN), precision="fp32",
+                   **({"rho_max": rho_max} if rho_max else {}))
     s.set_state(wl.x, wl.v)
-    s.step(500, integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=3)
+    s.step(steps, integrator="langevin", dt=wl.dt, kT=wl.kT, gamma=wl.gamma, seed=3)
     s.check()
     x = s.get_state()[0].cpu().numpy()
     n = s.count().cpu().numpy()
