@@ -78,14 +78,16 @@ def _col(row, *names):
 
 
 def trace_rows(d: str):
-    """(short name, duration ns, full name) per dispatch of a kernel-trace run."""
+    """(short name, duration ns, full name) per dispatch of a kernel-trace run, in the order
+    the dispatches started."""
     out = []
     for r in _read_rows(d, "kernel_trace.csv"):
         name = _col(r, "Kernel_Name", "KernelName")
         t0 = int(_col(r, "Start_Timestamp", "BeginNs"))
         t1 = int(_col(r, "End_Timestamp", "EndNs"))
-        out.append((short_name(name), t1 - t0, name))
-    return out
+        out.append((t0, short_name(name), t1 - t0, name))
+    out.sort(key=lambda t: t[0])
+    return [t[1:] for t in out]
 
 
 def split_builds(durs):
@@ -96,10 +98,14 @@ def split_builds(durs):
     return [d for d in durs if d > cut], [d for d in durs if d <= cut]
 
 
-def trace_summary(d: str):
+def trace_summary(d: str, last: int = 0):
+    """Per kernel: dispatches, mean, median and total duration (with last > 0, of its last
+    `last` dispatches only, e.g. the steps after a long relaxation)."""
     per = {}
     for k, dur, _ in trace_rows(d):
         per.setdefault(k, []).append(dur)
+    if last > 0:
+        per = {k: v[-last:] for k, v in per.items()}
     out = {}
     for k, durs in sorted(per.items()):
         e = {"dispatches": len(durs), "mean_us": statistics.fmean(durs) / 1e3,
@@ -230,6 +236,7 @@ def main(argv=None):
     t.add_argument("--out")
     t.add_argument("--title", default="")
     t.add_argument("--cmd", default="")
+    t.add_argument("--last", type=int, default=0, help="only each kernel's last N dispatches")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -247,7 +254,7 @@ def main(argv=None):
         print(json.dumps(rec["kernels"], indent=1))
         return 0
     if a.what == "trace":
-        summ = trace_summary(a.dir)
+        summ = trace_summary(a.dir, a.last)
         text = _md_trace(a.title, a.cmd, summ)
         if a.out:
             with open(a.out, "w") as fh:
